@@ -1,0 +1,154 @@
+/*
+ * kmeans.h -- C ABI of the MI355X two-stage (fast/slow) k-means library.
+ *
+ * Method: Salman, Kecman, Li, Strack and Test, "Fast k-means algorithm
+ * clustering" (arXiv 1108.1351), section 2 (Algorithm): Lloyd passes
+ * (squared distance, nearest center, cluster averages) first on a random
+ * fraction of the data starting from centers sampled from that fraction (the
+ * fast stage), then on the whole data starting from the fast stage's centers
+ * (the slow stage).  Readings of what the paper leaves open:
+ *   - distance is the squared Euclidean distance ("modified distance" of the
+ *     Algorithm, eq. (1) without the root); ties go to the lowest center index;
+ *   - J is eq. (3) taken as a sum over the points of the squared distance to
+ *     the nearest center;
+ *   - a stage stops after the pass whose largest center movement (Euclidean)
+ *     is below tol, or after max_iter passes (sections 5 and 6 stop on center
+ *     movement); that last pass is counted, as in Table 1;
+ *   - a cluster left without points keeps its center;
+ *   - the fast-stage subset holds m = min(n, max(k, floor(f*n + 0.5))) points,
+ *     those with the smallest keys key_i = SplitMix64 output i+1 for the seed
+ *     (Steele, Lea and Flood 2014); the initial centers are the k points with the
+ *     smallest keys, center j being the point with the j-th smallest key;
+ *   - labels and J are returned at the returned centers (one extra pass).
+ *
+ * Pointers.  X, centers and labels are DEVICE pointers (HIP, this process's
+ * current device), owned by the caller; the library never frees or keeps them
+ * after a call returns.  Info structs are HOST memory.  Rows are row-major,
+ * 64-bit indexed.
+ *
+ * Errors.  Every entry point returns a km_status and never aborts or throws.
+ * On a non-OK status the outputs are unspecified and kmeans_last_error()
+ * returns a message (thread-local, valid until the next call on that thread).
+ * Not converging within max_iter is not an error (converged[s] = 0).
+ *
+ * Determinism.  Cluster sums are exact 64-bit fixed-point integer sums and J
+ * is reduced in a fixed order, so a call repeated on the same inputs returns
+ * identical bits.
+ */
+#ifndef KMEANS_MI355X_H
+#define KMEANS_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KM_OK = 0,
+  KM_EINVAL = 1,      /* invalid argument (bad size, null pointer, NaN/Inf in X, ...) */
+  KM_ENOMEM = 2,      /* device allocation failed or the workspace is too small */
+  KM_EDEVICE = 3,     /* a HIP call failed; the message carries hipGetErrorString */
+  KM_EBUSY = 4,       /* resource in use (serving: queue full) */
+  KM_ECANCELLED = 5,  /* serving: the job was cancelled or the server destroyed */
+  KM_ETIMEOUT = 6,    /* serving: the wait timed out */
+  KM_ENOTFOUND = 7    /* serving: unknown ticket */
+} km_status;
+
+typedef enum { KM_F32 = 0, KM_BF16 = 1 } km_dtype;
+
+typedef enum {
+  KM_PREC_AUTO = 0,        /* FP32 for FP32 data, BF16 MFMA + re-rank for BF16 data with d >= 32 */
+  KM_PREC_FP32 = 1,        /* FP32 distances, FP64 check of uncertain points */
+  KM_PREC_BF16_RERANK = 2  /* BF16 MFMA x.c^T, FP32 re-rank of the top 4, FP64 check */
+} km_precision;
+
+typedef struct {
+  int32_t iters[2];      /* passes run in the fast and slow stage, incl. the one that met tol */
+  int32_t converged[2];  /* 1 if the stage stopped on shift < tol */
+  int32_t empty[2];      /* clusters with no member in the last pass of each stage */
+  int64_t m;             /* fast-stage subset size */
+  double J;              /* sum over all n points of the squared distance to the nearest returned center */
+  double J_stage1;       /* J of the last fast-stage pass (over the subset, at that pass's centers) */
+  int64_t dist_evals;    /* k*(m*iters[0] + n*iters[1]) + k*n: point-center distances the method needs */
+  double shift[2];       /* last largest center movement of each stage */
+  int64_t uncertain;     /* point labels decided by the FP64 check, summed over all passes */
+  double seconds[3];     /* wall time of sampling, fast stage, slow stage + final labels */
+} km_info;
+
+typedef struct {
+  km_dtype dtype;              /* element type of X */
+  km_precision precision;
+  int32_t max_iter[2];         /* per stage (fast, slow), >= 1 */
+  double tol[2];               /* per stage, >= 0 (0: run exactly max_iter passes) */
+  const double* init_centers;  /* optional HOST k*d FP64: replaces the sampled initial centers */
+  int32_t skip_stage1;         /* 1: slow stage only ("normal" k-means, or resume from init_centers) */
+  void* stream;                /* hipStream_t to run on; NULL = the null stream */
+  double* centers64_out;       /* optional DEVICE k*d FP64 copy of the returned centers */
+  double* J_hist;              /* optional HOST arrays of max_iter[0] + max_iter[1] entries: */
+  double* shift_hist;          /*   J and shift of every pass, fast stage first */
+} km_options;
+
+/*
+ * The two-stage method on FP32 data.  X: device n*d FP32.  centers_out: device
+ * k*d FP32.  labels_out: device n int32 (may be NULL).  info: host (may be NULL).
+ * Requires 1 <= k <= n, d >= 1, 0 < subset_frac <= 1, max_iter >= 1, tol >= 0.
+ * Runs on the null stream and returns when the result is in place.
+ */
+km_status kmeans_fit(const float* X, int64_t n, int32_t d, int32_t k, double subset_frac,
+                     uint64_t seed, int32_t max_iter, double tol, float* centers_out,
+                     int32_t* labels_out, km_info* info);
+
+/* As kmeans_fit with per-stage limits, BF16 data, a stream and a resume point.
+   opt may not be NULL (fill it with kmeans_default_options). */
+km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double subset_frac,
+                        uint64_t seed, const km_options* opt, float* centers_out,
+                        int32_t* labels_out, km_info* info);
+
+/* Options equivalent to kmeans_fit(max_iter, tol) on FP32 data. */
+void kmeans_default_options(km_options* opt, int32_t max_iter, double tol);
+
+/* Device bytes kmeans_fit_ex allocates for these sizes (0 on invalid sizes). */
+size_t kmeans_workspace_bytes(int64_t n, int32_t d, int32_t k, double subset_frac,
+                              const km_options* opt);
+
+/*
+ * Fast-stage sampling (Algorithm: "%per of S_n", "Select X_c from S_n
+ * randomly").  subset_idx: device m int64, ascending point indices of the
+ * subset; init_idx: device k int64, the initial centers' point indices in key
+ * order.  m must equal min(n, max(k, floor(f*n + 0.5))) for some f; any
+ * 1 <= k <= m <= n is accepted.  stream: hipStream_t or NULL.
+ */
+km_status km_sample(int64_t n, int64_t m, int32_t k, uint64_t seed, int64_t* subset_idx,
+                    int64_t* init_idx, void* stream);
+
+/*
+ * One Lloyd pass (Algorithm, one iteration of a While loop): nearest centers of
+ * the n rows of X (device, dtype) from centers C (device k*d FP64), cluster
+ * sums S (device k*d FP64, exact sums rounded once), counts N (device k int64),
+ * new centers C_new (device k*d FP64; an empty cluster keeps its center) and,
+ * in host memory, J, the largest center movement and the number of empty
+ * clusters.  labels (device n int32) may be NULL.
+ */
+km_status km_step(const void* X, km_dtype dtype, int64_t n, int32_t d, const double* C,
+                  int32_t k, km_precision precision, int32_t* labels, double* S, int64_t* N,
+                  double* C_new, double* J, double* shift, int32_t* empty, int64_t* uncertain,
+                  void* stream);
+
+/*
+ * Nearest center of every row (the Algorithm's assignment step, at fixed
+ * centers): labels (device n int32) and, in host memory, J = sum of the
+ * squared distances to those centers (eq. (3) as a sum).
+ */
+km_status km_assign(const void* X, km_dtype dtype, int64_t n, int32_t d, const double* C,
+                    int32_t k, km_precision precision, int32_t* labels, double* J,
+                    int64_t* uncertain, void* stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* kmeans_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMEANS_MI355X_H */

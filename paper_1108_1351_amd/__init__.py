@@ -1,0 +1,246 @@
+"""Python binding of the MI355X two-stage k-means library (``libkmeans_mi355x.so``).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory and the stream.  The functions carry the names
+of the C entry points declared in ``include/kmeans.h``.
+
+The method is the two-stage (fast/slow) k-means of Salman et al., "Fast
+k-means algorithm clustering" (arXiv 1108.1351), section 2 (Algorithm).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmeans_mi355x.so")
+
+KM_OK, KM_EINVAL, KM_ENOMEM, KM_EDEVICE, KM_EBUSY, KM_ECANCELLED, KM_ETIMEOUT, KM_ENOTFOUND = \
+    range(8)
+KM_F32, KM_BF16 = 0, 1
+PRECISION = {"auto": 0, "fp32": 1, "bf16_rerank": 2}
+EXPORTS = ("kmeans_fit", "kmeans_fit_ex", "kmeans_default_options", "kmeans_workspace_bytes",
+           "km_sample", "km_step", "km_assign", "kmeans_last_error")
+
+
+class KMeansError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"status {status}: {message}")
+        self.status = status
+
+
+class km_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32 * 2), ("converged", ctypes.c_int32 * 2),
+                ("empty", ctypes.c_int32 * 2), ("m", ctypes.c_int64), ("J", ctypes.c_double),
+                ("J_stage1", ctypes.c_double), ("dist_evals", ctypes.c_int64),
+                ("shift", ctypes.c_double * 2), ("uncertain", ctypes.c_int64),
+                ("seconds", ctypes.c_double * 3)]
+
+    def as_dict(self) -> dict:
+        return {"iters": list(self.iters), "converged": list(self.converged),
+                "empty": list(self.empty), "m": self.m, "J": self.J,
+                "J_stage1": self.J_stage1, "dist_evals": self.dist_evals,
+                "shift": list(self.shift), "uncertain": self.uncertain,
+                "seconds": list(self.seconds)}
+
+
+class km_options(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("precision", ctypes.c_int),
+                ("max_iter", ctypes.c_int32 * 2), ("tol", ctypes.c_double * 2),
+                ("init_centers", ctypes.c_void_p), ("skip_stage1", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("centers64_out", ctypes.c_void_p),
+                ("J_hist", ctypes.c_void_p), ("shift_hist", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library; fails loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is missing: run "
+                           "`python -c 'import __graft_entry__ as g; g.build()'` first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                              ctypes.c_double)
+    P = ctypes.POINTER
+    lib.kmeans_fit.argtypes = [vp, i64, i32, i32, f64, u64, i32, f64, vp, vp, P(km_info)]
+    lib.kmeans_fit_ex.argtypes = [vp, i64, i32, i32, f64, u64, P(km_options), vp, vp,
+                                  P(km_info)]
+    lib.kmeans_default_options.argtypes = [P(km_options), i32, f64]
+    lib.kmeans_default_options.restype = None
+    lib.kmeans_workspace_bytes.argtypes = [i64, i32, i32, f64, P(km_options)]
+    lib.kmeans_workspace_bytes.restype = ctypes.c_size_t
+    lib.km_sample.argtypes = [i64, i64, i32, u64, vp, vp, vp]
+    lib.km_step.argtypes = [vp, ctypes.c_int, i64, i32, vp, i32, ctypes.c_int, vp, vp, vp, vp,
+                            P(f64), P(f64), P(i32), P(i64), vp]
+    lib.km_assign.argtypes = [vp, ctypes.c_int, i64, i32, vp, i32, ctypes.c_int, vp, P(f64),
+                              P(i64), vp]
+    lib.kmeans_last_error.argtypes = []
+    lib.kmeans_last_error.restype = ctypes.c_char_p
+    for name in ("kmeans_fit", "kmeans_fit_ex", "km_sample", "km_step", "km_assign"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def kmeans_last_error() -> str:
+    return load().kmeans_last_error().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != KM_OK:
+        raise KMeansError(rc, kmeans_last_error())
+
+
+def _dtype_code(X: torch.Tensor) -> int:
+    if X.dtype == torch.float32:
+        return KM_F32
+    if X.dtype == torch.bfloat16:
+        return KM_BF16
+    raise TypeError(f"X must be float32 or bfloat16, got {X.dtype}")
+
+
+def _dev(t: torch.Tensor, name: str) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def _pair(v):
+    return (v[0], v[1]) if isinstance(v, (tuple, list)) else (v, v)
+
+
+def kmeans_fit(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter: int,
+               tol: float, labels: bool = True):
+    """The two-stage method on FP32 data (C: kmeans_fit).  Returns (centers, labels, info)."""
+    lib = load()
+    if X.dtype != torch.float32:
+        raise TypeError("kmeans_fit takes FP32 data; use kmeans_fit_ex for BF16")
+    n, d = X.shape
+    C = torch.empty((k, d), dtype=torch.float32, device=X.device)
+    L = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
+    info = km_info()
+    rc = lib.kmeans_fit(_dev(X, "X"), n, d, k, subset_frac, seed, max_iter, tol,
+                        C.data_ptr(), L.data_ptr() if L is not None else None,
+                        ctypes.byref(info))
+    _check(rc)
+    return C, L, info.as_dict()
+
+
+def kmeans_fit_ex(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter=50,
+                  tol=1e-4, *, precision: str = "auto", init_centers=None,
+                  skip_stage1: bool = False, labels: bool = True, centers64: bool = False,
+                  history: bool = False, stream=None):
+    """Per-stage limits, FP32 or BF16 data, resume point (C: kmeans_fit_ex).
+
+    Returns (centers FP32, labels or None, info dict); the dict also carries
+    ``centers64`` (device FP64) and ``J_hist`` / ``shift_hist`` when requested.
+    """
+    lib = load()
+    n, d = X.shape
+    opt = km_options()
+    mi, tl = _pair(max_iter), _pair(tol)
+    opt.dtype = _dtype_code(X)
+    opt.precision = PRECISION[precision]
+    opt.max_iter[0], opt.max_iter[1] = int(mi[0]), int(mi[1])
+    opt.tol[0], opt.tol[1] = float(tl[0]), float(tl[1])
+    opt.skip_stage1 = int(bool(skip_stage1))
+    opt.stream = _stream(stream)
+    ic = None
+    if init_centers is not None:
+        import numpy as np
+        ic = np.ascontiguousarray(init_centers, dtype=np.float64)
+        if ic.shape != (k, d):
+            raise ValueError("init_centers must have shape (k, d)")
+        opt.init_centers = ic.ctypes.data
+    C = torch.empty((k, d), dtype=torch.float32, device=X.device)
+    L = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
+    C64 = torch.empty((k, d), dtype=torch.float64, device=X.device) if centers64 else None
+    opt.centers64_out = C64.data_ptr() if C64 is not None else None
+    if history:
+        import numpy as np
+        jh = np.zeros(int(mi[0]) + int(mi[1]), np.float64)
+        sh = np.zeros_like(jh)
+        opt.J_hist, opt.shift_hist = jh.ctypes.data, sh.ctypes.data
+    info = km_info()
+    rc = lib.kmeans_fit_ex(_dev(X, "X"), n, d, k, subset_frac, seed, ctypes.byref(opt),
+                           C.data_ptr(), L.data_ptr() if L is not None else None,
+                           ctypes.byref(info))
+    _check(rc)
+    out = info.as_dict()
+    if C64 is not None:
+        out["centers64"] = C64
+    if history:
+        it = out["iters"]
+        out["J_hist"] = (jh[:it[0]].copy(), jh[int(mi[0]):int(mi[0]) + it[1]].copy())
+        out["shift_hist"] = (sh[:it[0]].copy(), sh[int(mi[0]):int(mi[0]) + it[1]].copy())
+    return C, L, out
+
+
+def kmeans_workspace_bytes(n: int, d: int, k: int, subset_frac: float, max_iter=50,
+                           dtype=torch.float32, skip_stage1: bool = False) -> int:
+    opt = km_options()
+    load().kmeans_default_options(ctypes.byref(opt), 1, 0.0)
+    mi = _pair(max_iter)
+    opt.max_iter[0], opt.max_iter[1] = int(mi[0]), int(mi[1])
+    opt.dtype = KM_F32 if dtype == torch.float32 else KM_BF16
+    opt.skip_stage1 = int(skip_stage1)
+    return int(load().kmeans_workspace_bytes(n, d, k, subset_frac, ctypes.byref(opt)))
+
+
+def km_sample(n: int, m: int, k: int, seed: int, device="cuda", stream=None):
+    """(subset indices ascending [m], initial-center indices in key order [k]) on the device."""
+    sub = torch.empty(m, dtype=torch.int64, device=device)
+    ini = torch.empty(k, dtype=torch.int64, device=device)
+    _check(load().km_sample(n, m, k, seed, sub.data_ptr(), ini.data_ptr(), _stream(stream)))
+    return sub, ini
+
+
+def km_step(X: torch.Tensor, C: torch.Tensor, precision: str = "auto", stream=None) -> dict:
+    """One Lloyd pass at centers C (device FP64 k x d)."""
+    n, d = X.shape
+    k = C.shape[0]
+    if C.dtype != torch.float64 or C.shape[1] != d:
+        raise ValueError("C must be FP64 with shape (k, d)")
+    lab = torch.empty(n, dtype=torch.int32, device=X.device)
+    S = torch.empty((k, d), dtype=torch.float64, device=X.device)
+    N = torch.empty(k, dtype=torch.int64, device=X.device)
+    Cn = torch.empty((k, d), dtype=torch.float64, device=X.device)
+    J, sh = ctypes.c_double(), ctypes.c_double()
+    em, un = ctypes.c_int32(), ctypes.c_int64()
+    rc = load().km_step(_dev(X, "X"), _dtype_code(X), n, d, _dev(C, "C"), k,
+                        PRECISION[precision], lab.data_ptr(), S.data_ptr(), N.data_ptr(),
+                        Cn.data_ptr(), ctypes.byref(J), ctypes.byref(sh), ctypes.byref(em),
+                        ctypes.byref(un), _stream(stream))
+    _check(rc)
+    return {"labels": lab, "S": S, "N": N, "C_new": Cn, "J": J.value, "shift": sh.value,
+            "empty": em.value, "uncertain": un.value}
+
+
+def km_assign(X: torch.Tensor, C: torch.Tensor, precision: str = "auto", stream=None):
+    """Nearest centers at fixed centers C (device FP64): (labels, J, uncertain)."""
+    n, d = X.shape
+    k = C.shape[0]
+    if C.dtype != torch.float64 or C.shape[1] != d:
+        raise ValueError("C must be FP64 with shape (k, d)")
+    lab = torch.empty(n, dtype=torch.int32, device=X.device)
+    J, un = ctypes.c_double(), ctypes.c_int64()
+    rc = load().km_assign(_dev(X, "X"), _dtype_code(X), n, d, _dev(C, "C"), k,
+                          PRECISION[precision], lab.data_ptr(), ctypes.byref(J),
+                          ctypes.byref(un), _stream(stream))
+    _check(rc)
+    return lab, J.value, un.value

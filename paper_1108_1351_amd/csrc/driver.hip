@@ -1,0 +1,543 @@
+// Host driver and C ABI (include/kmeans.h) of the two-stage k-means library.
+//
+// The two-stage loop follows the Algorithm of section 2 of Salman et al.
+// (arXiv 1108.1351): sample the fast-stage subset and the initial centers,
+// run Lloyd passes on the subset, then on the whole data from the subset's
+// centers, then label every point at the returned centers.  Each stage's pass
+// loop is enqueued in chunks of passes whose kernels return at once when the
+// device-side state says the stage has stopped; the host reads that state
+// after each chunk (one small copy), so it never waits on every pass.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kmeans.h"
+#include "km_internal.h"
+
+using namespace km;
+
+namespace {
+
+thread_local std::string g_err;
+
+km_status fail(km_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+km_status fail(km_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      rc = fail(KM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));             \
+      goto done;                                                                        \
+    }                                                                                   \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+size_t device_lds_limit() {
+  static std::mutex mu;
+  static std::vector<size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (!cache[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+      v = 65536;
+    cache[dev] = (size_t)v;
+  }
+  // leave room for the kernels' static LDS
+  return cache[dev] > 2048 ? cache[dev] - 2048 : cache[dev];
+}
+
+int64_t subset_size(int64_t n, int32_t k, double f) {
+  int64_t m = (int64_t)std::floor(f * (double)n + 0.5);
+  return std::min<int64_t>(n, std::max<int64_t>(k, m));
+}
+
+// Sub-allocations of one device block, 256-byte aligned.
+struct Carver {
+  size_t off = 0;
+  template <typename T>
+  size_t take(size_t count) {
+    size_t o = off;
+    off += (count * sizeof(T) + 255) / 256 * 256;
+    return o;
+  }
+};
+
+struct Layout {
+  size_t sel, hist, blk, sub, init_sel, init_key, xs, c64, cw, cn, cnorm, shiftj, emptyj, st,
+      jh, sh, part, part2, jpart, upart, labels;
+  size_t bytes;
+  bool labels_ws;
+};
+
+struct Sizes {
+  int64_t n, m;
+  int32_t d, k;
+  int elt;
+  bool stage1, sample;
+  int32_t hist_len;
+  PassPlan p1, p2;
+  bool need_labels_ws;
+};
+
+int64_t part_rows_max(const Sizes& z) {
+  return std::max(z.stage1 ? z.p1.part_rows : 0, z.p2.part_rows);
+}
+
+int64_t blocks_max(const Sizes& z) { return std::max(z.stage1 ? z.p1.blocks : 0, z.p2.blocks); }
+
+Layout make_layout(const Sizes& z) {
+  Layout L{};
+  Carver c;
+  const int64_t nmax = std::max<int64_t>(z.n, 1);
+  L.sel = c.take<SelState>(1);
+  L.hist = c.take<unsigned long long>(kSelBins);
+  L.blk = c.take<int64_t>((size_t)((nmax + kSelChunk - 1) / kSelChunk + 1));
+  L.sub = c.take<int64_t>((size_t)z.m);
+  L.init_sel = c.take<int64_t>((size_t)z.k);
+  L.init_key = c.take<int64_t>((size_t)z.k);
+  L.xs = c.take<unsigned char>(z.stage1 ? (size_t)z.m * z.d * z.elt : 0);
+  L.c64 = c.take<double>((size_t)z.k * z.d);
+  L.cw = c.take<float>((size_t)z.k * z.d);
+  L.cn = c.take<float>((size_t)z.k);
+  L.cnorm = c.take<double>((size_t)z.k);
+  L.shiftj = c.take<double>((size_t)z.k);
+  L.emptyj = c.take<int32_t>((size_t)z.k);
+  L.st = c.take<PassState>(1);
+  L.jh = c.take<double>((size_t)z.hist_len);
+  L.sh = c.take<double>((size_t)z.hist_len);
+  const size_t C = (size_t)z.k * (z.d + 1);
+  L.part = c.take<long long>((size_t)part_rows_max(z) * C);
+  L.part2 = c.take<long long>((size_t)32 * C);
+  L.jpart = c.take<double>((size_t)blocks_max(z));
+  L.upart = c.take<long long>((size_t)blocks_max(z));
+  L.labels_ws = z.need_labels_ws;
+  L.labels = c.take<int32_t>(z.need_labels_ws ? (size_t)z.n : 0);
+  L.bytes = c.off;
+  return L;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<unsigned char*>(base) + off);
+}
+
+bool valid_common(int64_t n, int32_t d, int32_t k) {
+  if (n < 1) return !fail(KM_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+  if (d < 1) return !fail(KM_EINVAL, "d must be >= 1 (got %d)", d);
+  if (k < 1) return !fail(KM_EINVAL, "k must be >= 1 (got %d)", k);
+  if (n > INT64_MAX / d) return !fail(KM_EINVAL, "n*d overflows int64");
+  if ((int64_t)k * (d + 1) > (1LL << 31)) return !fail(KM_EINVAL, "k*(d+1) too large");
+  return true;
+}
+
+// Device memory for one call: the caller's workspace or a stream-ordered allocation.
+struct DevMem {
+  void* ptr = nullptr;
+  bool owned = false;
+  hipStream_t s = nullptr;
+  km_status get(size_t bytes, void* ws, size_t ws_bytes, hipStream_t st) {
+    s = st;
+    if (ws) {
+      if (ws_bytes < bytes)
+        return fail(KM_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                    bytes);
+      ptr = ws;
+      return KM_OK;
+    }
+    hipError_t e = hipMallocAsync(&ptr, std::max<size_t>(bytes, 256), st);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return fail(KM_ENOMEM, "device allocation of %zu bytes failed: %s", bytes,
+                  hipGetErrorString(e));
+    }
+    owned = true;
+    return KM_OK;
+  }
+  ~DevMem() {
+    if (owned && ptr) {
+      (void)hipFreeAsync(ptr, s);
+    }
+  }
+};
+
+struct StageResult {
+  int32_t iters = 0, converged = 0, empty = 0;
+  double J = 0.0, shift = 0.0;
+  int64_t uncertain = 0;
+};
+
+// One stage's Lloyd loop on `rows` rows of Y.
+km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double tol,
+                    hipStream_t s, StageResult* out) {
+  km_status rc = KM_OK;
+  PassState hs;
+  int32_t launched = 0, chunk = 2;
+  const int64_t rows = b.n;
+  HIP_TRY(stage_reset(b.st, s));
+  HIP_TRY(max_abs(b.X, b.dtype, rows * b.d, b.st, s));
+  HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, s));
+  while (launched < max_iter) {
+    const int32_t q = std::min(chunk, max_iter - launched);
+    for (int32_t i = 0; i < q; ++i) HIP_TRY(lloyd_pass(b, plan, true, s));
+    launched += q;
+    chunk = std::min(chunk * 2, 16);
+    HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs.nonfinite) return fail(KM_EINVAL, "X contains NaN or Inf");
+    if (hs.done) break;
+  }
+  out->iters = hs.iter;
+  out->converged = hs.converged;
+  out->empty = hs.empty;
+  out->J = hs.J;
+  out->shift = hs.shift;
+  out->uncertain = hs.uncertain;
+done:
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kmeans_last_error(void) { return g_err.c_str(); }
+
+void kmeans_default_options(km_options* opt, int32_t max_iter, double tol) {
+  if (!opt) return;
+  memset(opt, 0, sizeof *opt);
+  opt->dtype = KM_F32;
+  opt->precision = KM_PREC_AUTO;
+  opt->max_iter[0] = opt->max_iter[1] = max_iter;
+  opt->tol[0] = opt->tol[1] = tol;
+}
+
+static bool fit_sizes(int64_t n, int32_t d, int32_t k, double f, const km_options* opt,
+                      bool labels_given, Sizes* z) {
+  if (!valid_common(n, d, k)) return false;
+  if (k > n) return !fail(KM_EINVAL, "k (%d) must not exceed n (%lld)", k, (long long)n);
+  if (!(f > 0.0 && f <= 1.0)) return !fail(KM_EINVAL, "subset_frac must be in (0, 1]");
+  if (opt->dtype != KM_F32 && opt->dtype != KM_BF16) return !fail(KM_EINVAL, "unknown dtype");
+  if (opt->precision == KM_PREC_BF16_RERANK)
+    return !fail(KM_EINVAL, "the BF16 MFMA precision path is not available in this build");
+  for (int s = 0; s < 2; ++s) {
+    if (opt->max_iter[s] < 1) return !fail(KM_EINVAL, "max_iter must be >= 1");
+    if (!(opt->tol[s] >= 0.0)) return !fail(KM_EINVAL, "tol must be >= 0 and not NaN");
+  }
+  z->n = n;
+  z->d = d;
+  z->k = k;
+  z->m = subset_size(n, k, f);
+  z->elt = opt->dtype == KM_F32 ? 4 : 2;
+  z->stage1 = !opt->skip_stage1;
+  z->sample = !(opt->skip_stage1 && opt->init_centers);
+  z->hist_len = opt->max_iter[0] + opt->max_iter[1];
+  const size_t lds = device_lds_limit();
+  z->p1 = plan_pass(z->m, d, k, lds);
+  z->p2 = plan_pass(n, d, k, lds);
+  z->need_labels_ws = !labels_given && ((z->stage1 && !z->p1.fused) || !z->p2.fused);
+  return true;
+}
+
+size_t kmeans_workspace_bytes(int64_t n, int32_t d, int32_t k, double subset_frac,
+                              const km_options* opt) {
+  km_options o;
+  if (!opt) {
+    kmeans_default_options(&o, 1, 0.0);
+    opt = &o;
+  }
+  Sizes z;
+  // sized for labels_out == NULL (the larger case)
+  if (!fit_sizes(n, d, k, subset_frac, opt, false, &z)) return 0;
+  return make_layout(z).bytes;
+}
+
+km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double subset_frac,
+                        uint64_t seed, const km_options* opt, float* centers_out,
+                        int32_t* labels_out, km_info* info) {
+  g_err.clear();
+  if (!opt) return fail(KM_EINVAL, "opt must not be NULL");
+  if (!X || !centers_out) return fail(KM_EINVAL, "X and centers_out must not be NULL");
+  Sizes z;
+  if (!fit_sizes(n, d, k, subset_frac, opt, labels_out != nullptr, &z)) return KM_EINVAL;
+  if (opt->init_centers)
+    for (int64_t e = 0; e < (int64_t)k * d; ++e)
+      if (!std::isfinite(opt->init_centers[e])) return fail(KM_EINVAL, "init_centers not finite");
+  hipStream_t s = (hipStream_t)opt->stream;
+  const Layout L = make_layout(z);
+  DevMem mem;
+  km_status rc = mem.get(L.bytes, nullptr, 0, s);
+  if (rc != KM_OK) return rc;
+  void* base = mem.ptr;
+  SelState* sel = at<SelState>(base, L.sel);
+  unsigned long long* hist = at<unsigned long long>(base, L.hist);
+  int64_t* blk = at<int64_t>(base, L.blk);
+  int64_t* sub = at<int64_t>(base, L.sub);
+  int64_t* init_sel = at<int64_t>(base, L.init_sel);
+  int64_t* init_key = at<int64_t>(base, L.init_key);
+  PassState* st = at<PassState>(base, L.st);
+  int32_t* lab_scratch = labels_out ? labels_out : (L.labels_ws ? at<int32_t>(base, L.labels) : nullptr);
+  StageResult r1, r2;
+  PassState hs;
+  std::vector<double> jh(z.hist_len), shh(z.hist_len);
+  const int dt = opt->dtype == KM_F32 ? 0 : 1;
+  const double t0 = now_s();
+  double t1 = t0, t2 = t0, t3 = t0;
+  PassBufs b{};
+  b.dtype = dt;
+  b.d = d;
+  b.k = k;
+  b.c64 = at<double>(base, L.c64);
+  b.cw = at<float>(base, L.cw);
+  b.cn = at<float>(base, L.cn);
+  b.cnorm = at<double>(base, L.cnorm);
+  b.shiftj = at<double>(base, L.shiftj);
+  b.emptyj = at<int32_t>(base, L.emptyj);
+  b.part = at<long long>(base, L.part);
+  b.part2 = at<long long>(base, L.part2);
+  b.Jpart = at<double>(base, L.jpart);
+  b.upart = at<long long>(base, L.upart);
+  b.st = st;
+  HIP_TRY(hipMemsetAsync(hist, 0, sizeof(unsigned long long) * kSelBins, s));
+
+  // ---- fast-stage subset and initial centers ("%per of S_n", "Select X_c")
+  if (z.sample) {
+    if (z.stage1) {
+      HIP_TRY(sel_run(nullptr, n, seed, z.m, sel, hist, blk, sub, s));
+      HIP_TRY(sel_run(sub, z.m, seed, k, sel, hist, blk, init_sel, s));
+    } else {
+      // the k smallest keys overall are the k smallest keys of the subset
+      HIP_TRY(sel_run(nullptr, n, seed, k, sel, hist, blk, init_sel, s));
+    }
+    HIP_TRY(rank_by_key(init_sel, k, seed, init_key, s));
+  } else if (z.stage1) {
+    HIP_TRY(sel_run(nullptr, n, seed, z.m, sel, hist, blk, sub, s));
+  }
+  if (opt->init_centers) {
+    HIP_TRY(hipMemcpyAsync(b.c64, opt->init_centers, sizeof(double) * k * d,
+                           hipMemcpyHostToDevice, s));
+  } else {
+    HIP_TRY(centers_from_rows(X, n, dt, d, init_key, k, b.c64, s));
+  }
+  if (z.stage1) HIP_TRY(gather_rows(X, n, dt, d, sub, z.m, at<unsigned char>(base, L.xs), s));
+  HIP_TRY(prep_centers(b.c64, k, d, b.cw, b.cn, b.cnorm, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  t1 = now_s();
+
+  // ---- fast stage on the subset
+  if (z.stage1) {
+    PassBufs b1 = b;
+    b1.X = at<unsigned char>(base, L.xs);
+    b1.n = z.m;
+    b1.labels = z.p1.fused ? nullptr : lab_scratch;
+    b1.J_hist = at<double>(base, L.jh);
+    b1.shift_hist = at<double>(base, L.sh);
+    rc = run_stage(b1, z.p1, opt->max_iter[0], opt->tol[0], s, &r1);
+    if (rc != KM_OK) goto done;
+  }
+  t2 = now_s();
+
+  // ---- slow stage on all points, from the fast stage's centers
+  {
+    PassBufs b2 = b;
+    b2.X = X;
+    b2.n = n;
+    b2.labels = z.p2.fused ? nullptr : lab_scratch;
+    b2.J_hist = at<double>(base, L.jh) + opt->max_iter[0];
+    b2.shift_hist = at<double>(base, L.sh) + opt->max_iter[0];
+    rc = run_stage(b2, z.p2, opt->max_iter[1], opt->tol[1], s, &r2);
+    if (rc != KM_OK) goto done;
+    // ---- labels and J at the returned centers
+    b2.labels = z.p2.fused ? labels_out : lab_scratch;
+    HIP_TRY(assign_only(b2, z.p2, s));
+  }
+  HIP_TRY(hipMemcpyAsync(centers_out, b.cw, sizeof(float) * k * d, hipMemcpyDeviceToDevice, s));
+  if (opt->centers64_out)
+    HIP_TRY(hipMemcpyAsync(opt->centers64_out, b.c64, sizeof(double) * k * d,
+                           hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(jh.data(), at<double>(base, L.jh), sizeof(double) * z.hist_len,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(shh.data(), at<double>(base, L.sh), sizeof(double) * z.hist_len,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  t3 = now_s();
+  if (info) {
+    memset(info, 0, sizeof *info);
+    info->iters[0] = r1.iters;
+    info->iters[1] = r2.iters;
+    info->converged[0] = r1.converged;
+    info->converged[1] = r2.converged;
+    info->empty[0] = r1.empty;
+    info->empty[1] = r2.empty;
+    info->m = z.m;
+    info->J = hs.J;
+    info->J_stage1 = r1.J;
+    info->shift[0] = r1.shift;
+    info->shift[1] = r2.shift;
+    info->dist_evals = (int64_t)k * (z.m * r1.iters + n * r2.iters) + (int64_t)k * n;
+    info->uncertain = r1.uncertain + hs.uncertain;
+    info->seconds[0] = t1 - t0;
+    info->seconds[1] = t2 - t1;
+    info->seconds[2] = t3 - t2;
+  }
+  if (opt->J_hist || opt->shift_hist) {
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int off = s2 == 0 ? 0 : opt->max_iter[0];
+      const int cnt = s2 == 0 ? r1.iters : r2.iters;
+      const int lim = s2 == 0 ? opt->max_iter[0] : opt->max_iter[1];
+      for (int i = 0; i < lim; ++i) {
+        if (opt->J_hist) opt->J_hist[off + i] = i < cnt ? jh[off + i] : 0.0;
+        if (opt->shift_hist) opt->shift_hist[off + i] = i < cnt ? shh[off + i] : 0.0;
+      }
+    }
+  }
+done:
+  if (rc != KM_OK) (void)hipStreamSynchronize(s);
+  return rc;
+}
+
+km_status kmeans_fit(const float* X, int64_t n, int32_t d, int32_t k, double subset_frac,
+                     uint64_t seed, int32_t max_iter, double tol, float* centers_out,
+                     int32_t* labels_out, km_info* info) {
+  km_options o;
+  kmeans_default_options(&o, max_iter, tol);
+  return kmeans_fit_ex(X, n, d, k, subset_frac, seed, &o, centers_out, labels_out, info);
+}
+
+km_status km_sample(int64_t n, int64_t m, int32_t k, uint64_t seed, int64_t* subset_idx,
+                    int64_t* init_idx, void* stream) {
+  g_err.clear();
+  if (n < 1 || k < 1 || m < k || m > n)
+    return fail(KM_EINVAL, "need 1 <= k <= m <= n (n=%lld m=%lld k=%d)", (long long)n,
+                (long long)m, k);
+  if (!subset_idx || !init_idx) return fail(KM_EINVAL, "null output pointer");
+  hipStream_t s = (hipStream_t)stream;
+  Carver c;
+  const size_t o_sel = c.take<SelState>(1), o_hist = c.take<unsigned long long>(kSelBins),
+               o_blk = c.take<int64_t>((size_t)((n + kSelChunk - 1) / kSelChunk + 1)),
+               o_is = c.take<int64_t>((size_t)k);
+  DevMem mem;
+  km_status rc = mem.get(c.off, nullptr, 0, s);
+  if (rc != KM_OK) return rc;
+  void* base = mem.ptr;
+  HIP_TRY(hipMemsetAsync(at<unsigned char>(base, o_hist), 0, sizeof(unsigned long long) * kSelBins, s));
+  HIP_TRY(sel_run(nullptr, n, seed, m, at<SelState>(base, o_sel),
+                  at<unsigned long long>(base, o_hist), at<int64_t>(base, o_blk), subset_idx, s));
+  HIP_TRY(sel_run(subset_idx, m, seed, k, at<SelState>(base, o_sel),
+                  at<unsigned long long>(base, o_hist), at<int64_t>(base, o_blk),
+                  at<int64_t>(base, o_is), s));
+  HIP_TRY(rank_by_key(at<int64_t>(base, o_is), k, seed, init_idx, s));
+  HIP_TRY(hipStreamSynchronize(s));
+done:
+  return rc;
+}
+
+// One pass (update) or a labelling (no update) at centers C.
+static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, const double* C,
+                          int32_t k, km_precision precision, int32_t* labels, double* S,
+                          int64_t* N, double* C_new, double* J, double* shift, int32_t* empty,
+                          int64_t* uncertain, void* stream, bool update) {
+  g_err.clear();
+  if (!valid_common(n, d, k)) return KM_EINVAL;
+  if (!X || !C) return fail(KM_EINVAL, "X and C must not be NULL");
+  if (dtype != KM_F32 && dtype != KM_BF16) return fail(KM_EINVAL, "unknown dtype");
+  if (precision == KM_PREC_BF16_RERANK)
+    return fail(KM_EINVAL, "the BF16 MFMA precision path is not available in this build");
+  hipStream_t s = (hipStream_t)stream;
+  const PassPlan p = plan_pass(n, d, k, device_lds_limit());
+  const bool lab_ws = !labels && !p.fused;
+  Carver c;
+  const size_t C_ = (size_t)k * (d + 1);
+  const size_t o_c64 = c.take<double>((size_t)k * d), o_cw = c.take<float>((size_t)k * d),
+               o_cn = c.take<float>(k), o_cnorm = c.take<double>(k),
+               o_sh = c.take<double>(k), o_em = c.take<int32_t>(k),
+               o_st = c.take<PassState>(1), o_part = c.take<long long>((size_t)p.part_rows * C_),
+               o_part2 = c.take<long long>(32 * C_), o_jp = c.take<double>((size_t)p.blocks),
+               o_up = c.take<long long>((size_t)p.blocks),
+               o_lab = c.take<int32_t>(lab_ws ? (size_t)n : 0);
+  DevMem mem;
+  km_status rc = mem.get(c.off, nullptr, 0, s);
+  if (rc != KM_OK) return rc;
+  void* base = mem.ptr;
+  PassState hs;
+  PassBufs b{};
+  b.X = X;
+  b.dtype = dtype == KM_F32 ? 0 : 1;
+  b.n = n;
+  b.d = d;
+  b.k = k;
+  b.c64 = at<double>(base, o_c64);
+  b.cw = at<float>(base, o_cw);
+  b.cn = at<float>(base, o_cn);
+  b.cnorm = at<double>(base, o_cnorm);
+  b.shiftj = at<double>(base, o_sh);
+  b.emptyj = at<int32_t>(base, o_em);
+  b.part = at<long long>(base, o_part);
+  b.part2 = at<long long>(base, o_part2);
+  b.Jpart = at<double>(base, o_jp);
+  b.upart = at<long long>(base, o_up);
+  b.labels = labels ? labels : (lab_ws ? at<int32_t>(base, o_lab) : nullptr);
+  b.st = at<PassState>(base, o_st);
+  b.S_out = S;
+  b.N_out = N;
+  HIP_TRY(hipMemcpyAsync(b.c64, C, sizeof(double) * k * d, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(prep_centers(b.c64, k, d, b.cw, b.cn, b.cnorm, s));
+  HIP_TRY(stage_reset(b.st, s));
+  HIP_TRY(max_abs(X, b.dtype, n * d, b.st, s));
+  HIP_TRY(stage_begin(b.st, 1, 0.0, n, b.cnorm, k, s));
+  HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hs.nonfinite) return fail(KM_EINVAL, "X contains NaN or Inf");
+  HIP_TRY(lloyd_pass(b, p, update, s));
+  if (update && C_new)
+    HIP_TRY(hipMemcpyAsync(C_new, b.c64, sizeof(double) * k * d, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (J) *J = hs.J;
+  if (shift) *shift = hs.shift;
+  if (empty) *empty = hs.empty;
+  if (uncertain) *uncertain = hs.uncertain;
+done:
+  return rc;
+}
+
+km_status km_step(const void* X, km_dtype dtype, int64_t n, int32_t d, const double* C,
+                  int32_t k, km_precision precision, int32_t* labels, double* S, int64_t* N,
+                  double* C_new, double* J, double* shift, int32_t* empty, int64_t* uncertain,
+                  void* stream) {
+  return one_pass(X, dtype, n, d, C, k, precision, labels, S, N, C_new, J, shift, empty,
+                  uncertain, stream, true);
+}
+
+km_status km_assign(const void* X, km_dtype dtype, int64_t n, int32_t d, const double* C,
+                    int32_t k, km_precision precision, int32_t* labels, double* J,
+                    int64_t* uncertain, void* stream) {
+  return one_pass(X, dtype, n, d, C, k, precision, labels, nullptr, nullptr, nullptr, J, nullptr,
+                  nullptr, uncertain, stream, false);
+}
+
+}  // extern "C"

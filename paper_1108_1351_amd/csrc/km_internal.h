@@ -1,0 +1,90 @@
+// Internal declarations shared by the kernel and driver translation units of
+// the MI355X k-means library.  Not part of the public ABI (include/kmeans.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace km {
+
+constexpr int kSelDigitBits = 12;
+constexpr int kSelBins = 1 << kSelDigitBits;
+constexpr int64_t kSelChunk = 8192;   // indices per block in the ordered compaction
+constexpr int kThreads = 256;          // threads per block of the point kernels
+
+// Progress of one radix selection of the r smallest 64-bit keys.  When done,
+// a key is selected iff its top `bits` bits are <= prefix (keys are distinct).
+struct SelState {
+  uint64_t prefix;
+  int64_t need;       // still to take from the bin `prefix`
+  int64_t bin_count;  // elements in the bin `prefix`
+  int32_t bits;
+  int32_t done;
+};
+
+// Device-resident state of one stage's Lloyd loop.
+struct PassState {
+  int32_t done;        // stage finished: kernels of later passes return at once
+  int32_t iter;        // passes run in this stage
+  int32_t max_iter;
+  int32_t F;           // cluster sums add rint(x * 2^F) as 64-bit integers
+  float scale;         // 2^F
+  float cmax;          // upper bound of max_j ||c_j||, for the FP32 error bound
+  uint32_t maxabs_bits;  // bits of max |x| over the stage's rows (NaN/Inf -> >= 0x7f800000)
+  int32_t nonfinite;
+  int32_t empty;
+  int32_t converged;
+  double tol;
+  double J;
+  double shift;
+  int64_t uncertain;   // labels settled by the FP64 check, cumulative over the stage
+  int64_t rows;
+};
+
+// Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
+hipError_t sel_run(const int64_t* idx_arr, int64_t count, uint64_t seed, int64_t r,
+                   SelState* st, unsigned long long* hist, int64_t* blk, int64_t* out,
+                   hipStream_t s);
+hipError_t rank_by_key(const int64_t* sel, int32_t k, uint64_t seed, int64_t* out,
+                       hipStream_t s);
+hipError_t gather_rows(const void* X, int64_t nrows, int dtype, int32_t d, const int64_t* idx,
+                       int64_t m, void* out, hipStream_t s);
+hipError_t centers_from_rows(const void* X, int64_t nrows, int dtype, int32_t d,
+                             const int64_t* idx, int32_t k, double* c64, hipStream_t s);
+hipError_t stage_reset(PassState* st, hipStream_t s);
+hipError_t max_abs(const void* X, int dtype, int64_t count, PassState* st, hipStream_t s);
+hipError_t prep_centers(const double* c64, int32_t k, int32_t d, float* cw, float* cn,
+                        double* cnorm, hipStream_t s);
+hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
+                       const double* cnorm, int32_t k, hipStream_t s);
+
+struct PassBufs {
+  const void* X; int dtype; int64_t n; int32_t d; int32_t k;
+  double* c64; float* cw; float* cn; double* cnorm;
+  double* shiftj; int32_t* emptyj;
+  long long* part; long long* part2; double* Jpart; long long* upart;
+  int32_t* labels;     // labels of the rows (required by the split path)
+  PassState* st;
+  double* J_hist; double* shift_hist;
+  double* S_out; int64_t* N_out;   // optional exact sums / counts of the pass
+};
+
+// Geometry chosen once per (rows, d, k): fused or split path and block counts.
+struct PassPlan {
+  bool fused;
+  int dmax;          // register tile of a row (0: generic)
+  int ppt;           // points per thread
+  int64_t blocks;    // blocks of the assign kernel (= partial rows in the fused path)
+  int64_t ublocks;   // point blocks of the split update kernel
+  int slice;         // dims per slice of the split update
+  int nslices;
+  int crange;        // centers per range of the split update
+  int64_t part_rows; // rows of `part`
+  size_t lds_assign, lds_update;
+  int ktile;         // centers per LDS tile (split assign)
+};
+
+PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, size_t lds_limit);
+hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
+hipError_t assign_only(const PassBufs& b, const PassPlan& p, hipStream_t s);
+
+}  // namespace km

@@ -1,0 +1,248 @@
+"""Parity of the HIP path with the FP64 oracle, called through the C ABI.
+
+One-step parity (km_assign, km_step) over a sweep of d and k at ragged n,
+adversarial ties and empty clusters, BF16 input, the sampler's index lists,
+end-to-end two-stage fits on every workload family at reduced n, determinism,
+and the 10M x 16 workload at full size on sampled outputs.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import (CTOL, GAP, JTOL, assert_centers, assert_labels, exempt_mask,
+                         to_device, widen)
+
+pytestmark = pytest.mark.gpu
+
+km = pytest.importorskip("paper_1108_1351_amd")
+
+
+def _mixture(n, d, k, seed, dtype="f32", spread=20.0):
+    spec = synth.MixtureSpec(d, k, "uniform", -spread, spread, sigma_lo=0.5, sigma_hi=2.0,
+                             weights="dirichlet1")
+    return synth.generate(spec, seed, n, dtype)
+
+
+def _centers_from(Xh, k, seed, jitter=0.3):
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(len(Xh), size=k, replace=len(Xh) < k)
+    return widen(Xh)[rows] + rng.normal(0.0, jitter, size=(k, Xh.shape[1]))
+
+
+# ------------------------------------------------------------------ sampling
+@pytest.mark.parametrize("n,m,k,seed", [(1, 1, 1, 0), (100, 10, 3, 5), (10_007, 101, 8, 7),
+                                        (100_000, 1000, 8, 1), (1 << 20, 4096, 64, 11),
+                                        (3_000_000, 3000, 1024, 2**64 - 1),
+                                        (10_000_000, 100_000, 64, 2), (5000, 5000, 17, 9)])
+def test_sample_matches_oracle(n, m, k, seed):
+    print(f"[sample] n={n} m={m} k={k}", flush=True)
+    sub, ini = km.km_sample(n, m, k, seed)
+    rsub, rini = oracle.select(n, m, k, seed)
+    assert np.array_equal(sub.cpu().numpy(), rsub)
+    assert np.array_equal(ini.cpu().numpy(), rini)
+
+
+# ------------------------------------------------------------ one-step parity
+SWEEP = [(1, 1), (1, 5), (2, 8), (3, 3), (4, 32), (5, 7), (8, 64), (16, 64), (17, 31),
+         (16, 1024), (32, 8), (32, 257), (64, 64), (100, 100), (128, 2), (128, 1024),
+         (129, 16), (200, 33), (2, 2000), (8, 5000)]
+
+
+@pytest.mark.parametrize("d,k", SWEEP)
+def test_assign_parity(d, k):
+    n = 10_007
+    print(f"[assign] n={n} d={d} k={k}", flush=True)
+    Xh = _mixture(n, d, min(k, 50), seed=d * 1000 + k)
+    C = _centers_from(Xh, k, seed=k)
+    lab, J, unc = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda())
+    ex = assert_labels(lab, Xh, C, name=f"assign d={d} k={k}")
+    rlab, D1, _ = oracle.assign(Xh, C)
+    assert abs(J - D1.sum()) <= 1e-12 * D1.sum()
+    assert ex <= 2
+
+
+@pytest.mark.parametrize("d,k", SWEEP)
+def test_step_parity(d, k):
+    n = 10_007
+    print(f"[step] n={n} d={d} k={k}", flush=True)
+    Xh = _mixture(n, d, min(k, 50), seed=d * 7 + k)
+    C = _centers_from(Xh, k, seed=k + 1)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    lab = out["labels"].cpu().numpy()
+    ex = exempt_mask(Xh, C)
+    assert np.array_equal(lab[~ex], ref.labels[~ex])
+    if np.array_equal(lab, ref.labels):
+        assert np.array_equal(out["N"].cpu().numpy(), ref.N)
+        # sums are exact sums of x rounded to a multiple of 2^-F, |x| 2^F < 2^30
+        amax = np.abs(widen(Xh)).max()
+        quantum = 2.0 ** (math.floor(math.log2(amax)) - 29) if amax > 0 else 0.0
+        S = out["S"].cpu().numpy()
+        assert np.all(np.abs(S - ref.S) <= ref.N[:, None] * quantum + 1e-12 * np.abs(ref.S))
+        assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9, name="C_new")
+        assert abs(out["shift"] - ref.shift) <= 1e-9 * max(1.0, ref.shift)
+        assert out["empty"] == ref.empty
+    assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
+
+
+def test_step_bf16_input():
+    Xh = _mixture(20_011, 64, 40, seed=3, dtype="bf16")
+    C = _centers_from(Xh, 40, seed=4)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    ex = exempt_mask(Xh, C)
+    assert np.array_equal(out["labels"].cpu().numpy()[~ex], ref.labels[~ex])
+    assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
+    assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9)
+
+
+# ---------------------------------------------------------------- adversarial
+def test_ties_go_to_lowest_index_and_empties_keep_center():
+    # points on the bisector of two centers, duplicated centers, a far center
+    xs = np.array([[0.0, y] for y in np.linspace(-3, 3, 301)], np.float32)
+    C = np.array([[1.0, 0.0], [-1.0, 0.0], [1.0, 0.0], [1e4, 1e4]])
+    out = km.km_step(to_device(xs), torch.from_numpy(C).cuda())
+    lab = out["labels"].cpu().numpy()
+    assert (lab == 0).all()
+    assert out["empty"] == 3 and out["N"].cpu().numpy().tolist() == [301, 0, 0, 0]
+    Cn = out["C_new"].cpu().numpy()
+    assert np.array_equal(Cn[1:], C[1:])
+    assert out["uncertain"] == 301
+    ref = oracle.step(xs, C)
+    assert np.array_equal(ref.labels, lab) and np.allclose(Cn, ref.C_new, atol=1e-12)
+
+
+def test_integer_grid_exact_ties():
+    g = np.stack(np.meshgrid(np.arange(-8, 9), np.arange(-8, 9)), -1).reshape(-1, 2)
+    Xh = np.repeat(g, 3, axis=0).astype(np.float32)
+    C = np.array([[-4.0, -4.0], [4.0, -4.0], [-4.0, 4.0], [4.0, 4.0], [0.0, 0.0]])
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    assert np.array_equal(out["labels"].cpu().numpy(), ref.labels)
+    assert np.array_equal(out["N"].cpu().numpy(), ref.N)
+    assert np.allclose(out["C_new"].cpu().numpy(), ref.C_new, rtol=0, atol=1e-12)
+
+
+def test_nonfinite_input_rejected():
+    Xh = _mixture(1000, 4, 3, seed=1)
+    Xh[17, 2] = np.nan
+    with pytest.raises(km.KMeansError) as e:
+        km.kmeans_fit(to_device(Xh), 3, 0.5, 0, 10, 1e-4)
+    assert e.value.status == km.KM_EINVAL
+
+
+# ------------------------------------------------------------------ end to end
+FITS = [
+    ("gmm2d_n1e5_k8", None),
+    ("gmm16d_n1e7_k64", 200_003),
+    ("gmm4d_n5e8_k32", 300_007),
+    ("gmm128d_n1e8_k1024_bf16", 40_009),
+]
+
+
+def _fit_both(w, Xh, **kw):
+    X = to_device(Xh)
+    C, L, info = km.kmeans_fit_ex(X, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol,
+                                  centers64=True, history=True, **kw)
+    ref = oracle.fit(Xh, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol, **kw)
+    return C, L, info, ref
+
+
+@pytest.mark.parametrize("name,n", FITS)
+def test_fit_parity(name, n):
+    w = synth.WORKLOADS[name]
+    if n is not None:
+        w = w.scaled(n)
+    print(f"[fit] {w.name} n={w.n} d={w.d} k={w.k}", flush=True)
+    Xh = w.data()
+    C, L, info, ref = _fit_both(w, Xh)
+    C64 = info["centers64"].cpu().numpy()
+    assert info["m"] == ref.info["m"]
+    assert info["iters"] == ref.info["iters"], (info["iters"], ref.info["iters"])
+    assert info["converged"] == ref.info["converged"]
+    assert info["empty"] == ref.info["empty"]
+    assert info["dist_evals"] == ref.info["dist_evals"]
+    assert_centers(C64, ref.centers, Xh, name=w.name)
+    assert np.allclose(C.cpu().numpy(), C64.astype(np.float32), rtol=0, atol=0)
+    assert abs(info["J"] - ref.info["J"]) <= JTOL * ref.info["J"]
+    for s in range(2):
+        assert np.allclose(info["J_hist"][s], ref.J_hist[s], rtol=JTOL, atol=0)
+    assert_labels(L, Xh, ref.centers, ref_labels=ref.labels, name=w.name)
+    assert_labels(L, Xh, C64, name=w.name + " at own centers")
+
+
+def test_fit_normal_mode_and_resume():
+    w = synth.WORKLOADS["gmm16d_n1e7_k64"].scaled(50_000)
+    Xh = w.data()
+    C, L, info, ref = _fit_both(w, Xh, skip_stage1=True)
+    assert info["iters"][0] == 0 and info["iters"] == ref.info["iters"]
+    assert_centers(info["centers64"].cpu().numpy(), ref.centers, Xh)
+    # resume the slow stage from given centers (a saved fast-stage result)
+    C0 = _centers_from(Xh, w.k, seed=5)
+    C, L, info, ref = _fit_both(w, Xh, skip_stage1=True, init_centers=C0)
+    assert info["iters"] == ref.info["iters"]
+    assert_centers(info["centers64"].cpu().numpy(), ref.centers, Xh)
+
+
+def test_fit_per_stage_tolerances():
+    w = synth.WORKLOADS["gmm2d_n1e5_k8"].scaled(30_000)
+    Xh = w.data()
+    X = to_device(Xh)
+    C, L, info = km.kmeans_fit_ex(X, w.k, 0.1, 3, (40, 60), (1e-3, 1e-6), centers64=True)
+    ref = oracle.fit(Xh, w.k, 0.1, 3, (40, 60), (1e-3, 1e-6))
+    assert info["iters"] == ref.info["iters"]
+    assert_centers(info["centers64"].cpu().numpy(), ref.centers, Xh)
+
+
+def test_deterministic_bits():
+    w = synth.WORKLOADS["gmm16d_n1e7_k64"].scaled(100_000)
+    X = to_device(w.data())
+    a = km.kmeans_fit_ex(X, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol, centers64=True)
+    b = km.kmeans_fit_ex(X, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol, centers64=True)
+    assert torch.equal(a[2]["centers64"], b[2]["centers64"])
+    assert torch.equal(a[1], b[1])
+    assert a[2]["J"] == b[2]["J"] and a[2]["iters"] == b[2]["iters"]
+
+
+def test_kmeans_fit_plain_entry_point():
+    w = synth.WORKLOADS["gmm2d_n1e5_k8"]
+    Xh = w.data()
+    C, L, info = km.kmeans_fit(to_device(Xh), w.k, w.subset_frac, w.fit_seed, w.max_iter,
+                               w.tol)
+    ref = oracle.fit(Xh, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol)
+    assert info["iters"] == ref.info["iters"]
+    assert_centers(C.cpu().numpy().astype(np.float64), ref.centers, Xh)
+    assert abs(info["J"] - ref.info["J"]) <= JTOL * ref.info["J"]
+
+
+# ------------------------------------------------------- full-size workload
+def test_full_size_16d_sampled_outputs():
+    """10M x 16, k = 64, as timed by the benchmark: the oracle checks labels on a
+    sample of rows, J over all rows, and one pass at the returned centers."""
+    w = synth.WORKLOADS["gmm16d_n1e7_k64"]
+    print(f"[full] {w.name}: generating {w.n} x {w.d}", flush=True)
+    Xh = w.data()
+    X = to_device(Xh)
+    C, L, info = km.kmeans_fit_ex(X, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol,
+                                  centers64=True)
+    print(f"[full] fit done iters={info['iters']} uncertain={info['uncertain']}", flush=True)
+    C64 = info["centers64"].cpu().numpy()
+    lab = L.cpu().numpy()
+    rows = np.random.default_rng(0).choice(w.n, 200_000, replace=False)
+    rows.sort()
+    assert_labels(lab[rows], np.ascontiguousarray(Xh[rows]), C64, name="sampled rows")
+    _, D1, _ = oracle.assign(Xh, C64)
+    assert abs(info["J"] - D1.sum()) <= JTOL * D1.sum()
+    # one pass at the returned centers: identical sums and movement on all rows
+    out = km.km_step(X, info["centers64"])
+    ref = oracle.step(Xh, C64)
+    ex = exempt_mask(Xh[rows], C64)
+    assert np.array_equal(out["labels"].cpu().numpy()[rows][~ex], ref.labels[rows][~ex])
+    assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9)
+    assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
+    if info["converged"][1]:
+        assert ref.shift < w.tol * 1.01
