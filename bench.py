@@ -1,0 +1,192 @@
+#!/usr/bin/env python
+"""Benchmark of the two-stage k-means hot path on one MI355X.
+
+A step is one complete two-stage fit -- fast-stage sampling, the fast stage on
+the subset, the slow stage on all points, the final labelling pass -- of the
+10,000,000 x 16-D, k = 64 Gaussian-mixture workload (FP32), with X resident in
+HBM before the timed region.  ``value`` is distance evaluations per second of
+the whole job: k*(m*Q_f + n*Q_s) + k*n evaluations per fit (section 3 of the
+paper counts the method's cost in these units) over the fit's wall time.
+
+The roofline object covers the dominant kernel, the slow stage's assignment
+kernel: its duration is measured live with HIP events on the stream it runs
+on (the library's pass profiler), and its algorithmic work per launch is
+2*n*k*d FP32 flops and n*d*4 bytes.  The CPU baseline is the FP64 oracle
+timed on a bounded sample of the same workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "gmm16d_n1e7_k64"
+PEAK_FP32_TFLOPS = 157.3        # MI355X published FP32 vector/matrix peak
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
+METRIC = "distance evals/s & % roofline per Lloyd iter; batched p50/p99 solve latency"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "km_internal.h"):
+        with open(os.path.join(ROOT, "paper_1108_1351_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is absent or the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_assign_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        parts = line.strip().split(None, 1)
+        if len(parts) == 2 and not line.startswith("#"):
+            kv[parts[0]] = parts[1]
+    if kv.get("kernel_src_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(w, rows: int):
+    import oracle
+    Xs = w.data(n=rows)
+    t0 = time.perf_counter()
+    f = oracle.fit(Xs, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol)
+    dt = time.perf_counter() - t0
+    return {"value": f.info["dist_evals"] / dt, "unit": "distance evals/s",
+            "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": (f"full two-stage fit of the first {rows:,} rows of {w.name} "
+                       f"(same k, subset fraction, seed, max_iter, tol): "
+                       f"{f.info['dist_evals']:.3e} evals in {dt:.2f} s, "
+                       f"passes {f.info['iters']}")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--cpu-rows", type=int, default=2_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (HBM counter scale)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1108_1351_amd as km
+    import synth
+
+    w = synth.WORKLOADS[args.workload]
+    print(f"[bench] generating {w.name}: n={w.n} d={w.d} k={w.k} {w.dtype}", file=sys.stderr,
+          flush=True)
+    host = torch.empty((w.n, w.d), dtype=torch.float32 if w.dtype == "f32" else torch.int16,
+                       pin_memory=True)
+    hv = host.numpy() if w.dtype == "f32" else host.numpy().view(np.uint16)
+    w.data(out=hv)
+    X = host.to("cuda", non_blocking=False)
+    if w.dtype == "bf16":
+        X = X.view(torch.bfloat16)
+    del host
+    torch.cuda.synchronize()
+
+    def step():
+        return km.kmeans_fit_ex(X, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol,
+                                labels=True)
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    evals = 0
+    infos = []
+    km.kmeans_profile_begin()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, _, info = step()
+        evals += info["dist_evals"]
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = km.kmeans_profile_end()
+    print(f"[bench] timed {args.steps} steps in {t1 - t0:.3f} s", file=sys.stderr, flush=True)
+    dt = t1 - t0
+    value = evals / dt
+    info = infos[-1]
+
+    # dominant kernel: the slow stage's assignment kernel (one launch per pass)
+    launches = prof["passes"][1]
+    avg_s = prof["assign_ms"][1] / 1e3 / max(1, launches)
+    rows = prof["rows"][1] / max(1, launches)
+    flops = 2.0 * rows * w.k * w.d
+    algo_bytes = rows * w.d * (4 if w.dtype == "f32" else 2)
+    achieved = flops / avg_s / 1e12
+    traffic = read_traffic(w.name)
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": traffic,
+                "kernel": "slow-stage assignment kernel (fused assign + cluster sums)",
+                "launches": launches, "avg_launch_us": avg_s * 1e6,
+                "flops_per_launch": flops, "algo_bytes_per_launch": algo_bytes,
+                "algo_hbm_GBs": algo_bytes / avg_s / 1e9}
+    pass_s = prof["pass_ms"][1] / 1e3 / max(1, launches)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "distance evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.dtype == "f32" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k,
+                   "subset_frac": w.subset_frac, "max_iter": w.max_iter, "tol": w.tol,
+                   "passes": info["iters"], "m": info["m"],
+                   "dist_evals_per_fit": info["dist_evals"]},
+        "per_pass": {"slow_stage_pass_us": pass_s * 1e6,
+                     "slow_stage_evals_per_s": rows * w.k / pass_s,
+                     "assign_evals_per_s": rows * w.k / avg_s},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline on {args.cpu_rows} rows", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -145,6 +145,27 @@ km_status km_assign(const void* X, km_dtype dtype, int64_t n, int32_t d, const d
                     int32_t k, km_precision precision, int32_t* labels, double* J,
                     int64_t* uncertain, void* stream);
 
+/*
+ * Pass timing, for measuring the library against the roofline.  Between
+ * kmeans_profile_begin() and kmeans_profile_end(), every fit records HIP events
+ * on its stream around each Lloyd pass and around the pass's assignment kernel
+ * (the dominant kernel); only passes that ran are counted.  Process-wide;
+ * fits that overlap in time are all counted.  out may be NULL.
+ */
+typedef struct {
+  int64_t fits;          /* fits completed while profiling */
+  int64_t passes[2];     /* Lloyd passes run, fast and slow stage */
+  int64_t rows[2];       /* rows processed by those passes' assignment kernels */
+  double assign_ms[2];   /* summed duration of the assignment kernels */
+  double pass_ms[2];     /* summed duration of whole passes (assign through stop decision) */
+} km_prof;
+
+km_status kmeans_profile_begin(void);
+km_status kmeans_profile_end(km_prof* out);
+
+/* Return the device memory the library keeps for reuse between calls. */
+km_status kmeans_release_memory(void);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char* kmeans_last_error(void);
 

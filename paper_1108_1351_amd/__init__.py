@@ -22,7 +22,8 @@ KM_OK, KM_EINVAL, KM_ENOMEM, KM_EDEVICE, KM_EBUSY, KM_ECANCELLED, KM_ETIMEOUT, K
 KM_F32, KM_BF16 = 0, 1
 PRECISION = {"auto": 0, "fp32": 1, "bf16_rerank": 2}
 EXPORTS = ("kmeans_fit", "kmeans_fit_ex", "kmeans_default_options", "kmeans_workspace_bytes",
-           "km_sample", "km_step", "km_assign", "kmeans_last_error")
+           "km_sample", "km_step", "km_assign", "kmeans_last_error", "kmeans_profile_begin",
+           "kmeans_profile_end", "kmeans_release_memory")
 
 
 class KMeansError(RuntimeError):
@@ -54,6 +55,16 @@ class km_options(ctypes.Structure):
                 ("J_hist", ctypes.c_void_p), ("shift_hist", ctypes.c_void_p)]
 
 
+class km_prof(ctypes.Structure):
+    _fields_ = [("fits", ctypes.c_int64), ("passes", ctypes.c_int64 * 2),
+                ("rows", ctypes.c_int64 * 2), ("assign_ms", ctypes.c_double * 2),
+                ("pass_ms", ctypes.c_double * 2)]
+
+    def as_dict(self) -> dict:
+        return {"fits": self.fits, "passes": list(self.passes), "rows": list(self.rows),
+                "assign_ms": list(self.assign_ms), "pass_ms": list(self.pass_ms)}
+
+
 _lib = None
 
 
@@ -81,9 +92,13 @@ def load():
                             P(f64), P(f64), P(i32), P(i64), vp]
     lib.km_assign.argtypes = [vp, ctypes.c_int, i64, i32, vp, i32, ctypes.c_int, vp, P(f64),
                               P(i64), vp]
+    lib.kmeans_profile_begin.argtypes = []
+    lib.kmeans_profile_end.argtypes = [P(km_prof)]
+    lib.kmeans_release_memory.argtypes = []
     lib.kmeans_last_error.argtypes = []
     lib.kmeans_last_error.restype = ctypes.c_char_p
-    for name in ("kmeans_fit", "kmeans_fit_ex", "km_sample", "km_step", "km_assign"):
+    for name in ("kmeans_fit", "kmeans_fit_ex", "km_sample", "km_step", "km_assign",
+                 "kmeans_profile_begin", "kmeans_profile_end", "kmeans_release_memory"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -244,3 +259,17 @@ def km_assign(X: torch.Tensor, C: torch.Tensor, precision: str = "auto", stream=
                           ctypes.byref(un), _stream(stream))
     _check(rc)
     return lab, J.value, un.value
+
+
+def kmeans_profile_begin() -> None:
+    _check(load().kmeans_profile_begin())
+
+
+def kmeans_profile_end() -> dict:
+    out = km_prof()
+    _check(load().kmeans_profile_end(ctypes.byref(out)))
+    return out.as_dict()
+
+
+def kmeans_release_memory() -> None:
+    _check(load().kmeans_release_memory())

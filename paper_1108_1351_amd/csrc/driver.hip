@@ -154,6 +154,31 @@ bool valid_common(int64_t n, int32_t d, int32_t k) {
   return true;
 }
 
+// Per-device stream-ordered pool that keeps freed blocks for reuse, so the
+// workspace of repeated calls costs no new device mapping.
+std::mutex g_pool_mu;
+std::vector<hipMemPool_t> g_pools;
+
+hipMemPool_t device_pool() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1, nullptr);
+  if (!g_pools[dev]) {
+    hipMemPoolProps props;
+    memset(&props, 0, sizeof props);
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
+    uint64_t thr = UINT64_MAX;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    g_pools[dev] = pool;
+  }
+  return g_pools[dev];
+}
+
 // Device memory for one call: the caller's workspace or a stream-ordered allocation.
 struct DevMem {
   void* ptr = nullptr;
@@ -168,7 +193,9 @@ struct DevMem {
       ptr = ws;
       return KM_OK;
     }
-    hipError_t e = hipMallocAsync(&ptr, std::max<size_t>(bytes, 256), st);
+    hipMemPool_t pool = device_pool();
+    hipError_t e = pool ? hipMallocFromPoolAsync(&ptr, std::max<size_t>(bytes, 256), pool, st)
+                        : hipMallocAsync(&ptr, std::max<size_t>(bytes, 256), st);
     if (e != hipSuccess) {
       ptr = nullptr;
       return fail(KM_ENOMEM, "device allocation of %zu bytes failed: %s", bytes,
@@ -184,6 +211,39 @@ struct DevMem {
   }
 };
 
+// Event timing of the passes (kmeans_profile_begin / _end).
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> free_events;
+  km_prof acc;
+};
+Prof g_prof;
+
+hipEvent_t take_event() {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!g_prof.free_events.empty()) {
+    hipEvent_t e = g_prof.free_events.back();
+    g_prof.free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void give_events(std::vector<hipEvent_t>& evs) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (hipEvent_t e : evs)
+    if (e) g_prof.free_events.push_back(e);
+  evs.clear();
+}
+
+bool prof_on() {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  return g_prof.on;
+}
+
 struct StageResult {
   int32_t iters = 0, converged = 0, empty = 0;
   double J = 0.0, shift = 0.0;
@@ -192,17 +252,28 @@ struct StageResult {
 
 // One stage's Lloyd loop on `rows` rows of Y.
 km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double tol,
-                    hipStream_t s, StageResult* out) {
+                    hipStream_t s, StageResult* out, int stage) {
   km_status rc = KM_OK;
   PassState hs;
   int32_t launched = 0, chunk = 2;
   const int64_t rows = b.n;
+  const bool prof = prof_on();
+  std::vector<hipEvent_t> ev;
+  if (prof)
+    for (int32_t i = 0; i < 3 * max_iter; ++i) ev.push_back(take_event());
   HIP_TRY(stage_reset(b.st, s));
   HIP_TRY(max_abs(b.X, b.dtype, rows * b.d, b.st, s));
   HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, s));
   while (launched < max_iter) {
     const int32_t q = std::min(chunk, max_iter - launched);
-    for (int32_t i = 0; i < q; ++i) HIP_TRY(lloyd_pass(b, plan, true, s));
+    for (int32_t i = 0; i < q; ++i) {
+      const int32_t t = launched + i;
+      if (prof && ev[3 * t]) HIP_TRY(hipEventRecord(ev[3 * t], s));
+      HIP_TRY(pass_assign(b, plan, true, s));
+      if (prof && ev[3 * t + 1]) HIP_TRY(hipEventRecord(ev[3 * t + 1], s));
+      HIP_TRY(pass_rest(b, plan, true, s));
+      if (prof && ev[3 * t + 2]) HIP_TRY(hipEventRecord(ev[3 * t + 2], s));
+    }
     launched += q;
     chunk = std::min(chunk * 2, 16);
     HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
@@ -216,7 +287,28 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
   out->J = hs.J;
   out->shift = hs.shift;
   out->uncertain = hs.uncertain;
+  if (prof) {
+    // only the first hs.iter passes ran; later ones returned at once
+    double a = 0.0, p = 0.0;
+    bool ok = true;
+    for (int32_t t = 0; t < hs.iter && ok; ++t) {
+      float ea = 0.f, ep = 0.f;
+      ok = ev[3 * t] && ev[3 * t + 1] && ev[3 * t + 2] &&
+           hipEventElapsedTime(&ea, ev[3 * t], ev[3 * t + 1]) == hipSuccess &&
+           hipEventElapsedTime(&ep, ev[3 * t], ev[3 * t + 2]) == hipSuccess;
+      a += ea;
+      p += ep;
+    }
+    if (ok) {
+      std::lock_guard<std::mutex> lk(g_prof.mu);
+      g_prof.acc.passes[stage] += hs.iter;
+      g_prof.acc.rows[stage] += (int64_t)hs.iter * rows;
+      g_prof.acc.assign_ms[stage] += a;
+      g_prof.acc.pass_ms[stage] += p;
+    }
+  }
 done:
+  if (!ev.empty()) give_events(ev);
   return rc;
 }
 
@@ -225,6 +317,32 @@ done:
 extern "C" {
 
 const char* kmeans_last_error(void) { return g_err.c_str(); }
+
+km_status kmeans_profile_begin(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  memset(&g_prof.acc, 0, sizeof g_prof.acc);
+  g_prof.on = true;
+  return KM_OK;
+}
+
+km_status kmeans_profile_end(km_prof* out) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = false;
+  if (out) *out = g_prof.acc;
+  return KM_OK;
+}
+
+km_status kmeans_release_memory(void) {
+  g_err.clear();
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (hipMemPool_t p : g_pools)
+    if (p) {
+      hipError_t e = hipMemPoolTrimTo(p, 0);
+      if (e != hipSuccess)
+        return fail(KM_EDEVICE, "hipMemPoolTrimTo failed: %s", hipGetErrorString(e));
+    }
+  return KM_OK;
+}
 
 void kmeans_default_options(km_options* opt, int32_t max_iter, double tol) {
   if (!opt) return;
@@ -355,7 +473,7 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
     b1.labels = z.p1.fused ? nullptr : lab_scratch;
     b1.J_hist = at<double>(base, L.jh);
     b1.shift_hist = at<double>(base, L.sh);
-    rc = run_stage(b1, z.p1, opt->max_iter[0], opt->tol[0], s, &r1);
+    rc = run_stage(b1, z.p1, opt->max_iter[0], opt->tol[0], s, &r1, 0);
     if (rc != KM_OK) goto done;
   }
   t2 = now_s();
@@ -368,7 +486,7 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
     b2.labels = z.p2.fused ? nullptr : lab_scratch;
     b2.J_hist = at<double>(base, L.jh) + opt->max_iter[0];
     b2.shift_hist = at<double>(base, L.sh) + opt->max_iter[0];
-    rc = run_stage(b2, z.p2, opt->max_iter[1], opt->tol[1], s, &r2);
+    rc = run_stage(b2, z.p2, opt->max_iter[1], opt->tol[1], s, &r2, 1);
     if (rc != KM_OK) goto done;
     // ---- labels and J at the returned centers
     b2.labels = z.p2.fused ? labels_out : lab_scratch;
@@ -385,6 +503,10 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   t3 = now_s();
+  if (prof_on()) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.acc.fits += 1;
+  }
   if (info) {
     memset(info, 0, sizeof *info);
     info->iters[0] = r1.iters;

@@ -1056,7 +1056,7 @@ static void reduce_finalize_conclude(const PassBufs& b, const PassPlan& p, const
                      b.shift_hist);
 }
 
-hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
+hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
   const int32_t* gate = update ? &b.st->done : nullptr;
   if (p.fused) {
     if (b.dtype == 0) dispatch_fused<float>(b, p, update, gate, s);
@@ -1064,9 +1064,14 @@ hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStre
   } else {
     if (b.dtype == 0) dispatch_tiled<float>(b, p, gate, s);
     else dispatch_tiled<uint16_t>(b, p, gate, s);
-    if (update) split_update(b, p, gate, s);
   }
+  return hipGetLastError();
+}
+
+hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
+  const int32_t* gate = update ? &b.st->done : nullptr;
   if (update) {
+    if (!p.fused) split_update(b, p, gate, s);
     reduce_finalize_conclude(b, p, gate, s);
   } else {
     hipLaunchKernelGGL(k_conclude, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
@@ -1075,6 +1080,12 @@ hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStre
                        nullptr);
   }
   return hipGetLastError();
+}
+
+hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
+  hipError_t e = pass_assign(b, p, update, s);
+  if (e != hipSuccess) return e;
+  return pass_rest(b, p, update, s);
 }
 
 hipError_t assign_only(const PassBufs& b, const PassPlan& p, hipStream_t s) {

@@ -85,6 +85,9 @@ struct PassPlan {
 
 PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, size_t lds_limit);
 hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
+// the assignment kernel of a pass, and everything after it (update, reduction, stop test)
+hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
+hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
 hipError_t assign_only(const PassBufs& b, const PassPlan& p, hipStream_t s);
 
 }  // namespace km
