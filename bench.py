@@ -173,7 +173,9 @@ def main() -> int:
         "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k,
                    "subset_frac": w.subset_frac, "max_iter": w.max_iter, "tol": w.tol,
                    "passes": info["iters"], "m": info["m"],
-                   "dist_evals_per_fit": info["dist_evals"]},
+                   "dist_evals_per_fit": info["dist_evals"],
+                   "fp64_full_checks_per_fit": info["uncertain"],
+                   "fp64_pair_decisions_per_fit": info["fp64_pairs"]},
         "per_pass": {"slow_stage_pass_us": pass_s * 1e6,
                      "slow_stage_evals_per_s": rows * w.k / pass_s,
                      "assign_evals_per_s": rows * w.k / avg_s},

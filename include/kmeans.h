@@ -73,8 +73,9 @@ typedef struct {
   double J_stage1;       /* J of the last fast-stage pass (over the subset, at that pass's centers) */
   int64_t dist_evals;    /* k*(m*iters[0] + n*iters[1]) + k*n: point-center distances the method needs */
   double shift[2];       /* last largest center movement of each stage */
-  int64_t uncertain;     /* point labels decided by the FP64 check, summed over all passes */
+  int64_t uncertain;     /* labels decided by the FP64 check over all centers, summed over passes */
   double seconds[3];     /* wall time of sampling, fast stage, slow stage + final labels */
+  int64_t fp64_pairs;    /* labels decided by FP64 distances to the best two candidates */
 } km_info;
 
 typedef struct {

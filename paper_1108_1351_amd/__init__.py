@@ -37,14 +37,14 @@ class km_info(ctypes.Structure):
                 ("empty", ctypes.c_int32 * 2), ("m", ctypes.c_int64), ("J", ctypes.c_double),
                 ("J_stage1", ctypes.c_double), ("dist_evals", ctypes.c_int64),
                 ("shift", ctypes.c_double * 2), ("uncertain", ctypes.c_int64),
-                ("seconds", ctypes.c_double * 3)]
+                ("seconds", ctypes.c_double * 3), ("fp64_pairs", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {"iters": list(self.iters), "converged": list(self.converged),
                 "empty": list(self.empty), "m": self.m, "J": self.J,
                 "J_stage1": self.J_stage1, "dist_evals": self.dist_evals,
                 "shift": list(self.shift), "uncertain": self.uncertain,
-                "seconds": list(self.seconds)}
+                "fp64_pairs": self.fp64_pairs, "seconds": list(self.seconds)}
 
 
 class km_options(ctypes.Structure):

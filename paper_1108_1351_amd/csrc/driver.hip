@@ -52,6 +52,23 @@ double now_s() {
       .count();
 }
 
+int device_cus() {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (!cache[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        v <= 0)
+      v = 256;
+    cache[dev] = v;
+  }
+  return cache[dev];
+}
+
 size_t device_lds_limit() {
   static std::mutex mu;
   static std::vector<size_t> cache;
@@ -88,7 +105,7 @@ struct Carver {
 
 struct Layout {
   size_t sel, hist, blk, sub, init_sel, init_key, xs, c64, cw, cn, cnorm, shiftj, emptyj, st,
-      jh, sh, part, part2, jpart, upart, labels;
+      jh, sh, slots, jpart, upart, labels;
   size_t bytes;
   bool labels_ws;
 };
@@ -102,10 +119,6 @@ struct Sizes {
   PassPlan p1, p2;
   bool need_labels_ws;
 };
-
-int64_t part_rows_max(const Sizes& z) {
-  return std::max(z.stage1 ? z.p1.part_rows : 0, z.p2.part_rows);
-}
 
 int64_t blocks_max(const Sizes& z) { return std::max(z.stage1 ? z.p1.blocks : 0, z.p2.blocks); }
 
@@ -130,10 +143,9 @@ Layout make_layout(const Sizes& z) {
   L.jh = c.take<double>((size_t)z.hist_len);
   L.sh = c.take<double>((size_t)z.hist_len);
   const size_t C = (size_t)z.k * (z.d + 1);
-  L.part = c.take<long long>((size_t)part_rows_max(z) * C);
-  L.part2 = c.take<long long>((size_t)32 * C);
+  L.slots = c.take<long long>((size_t)kSlots * C);
   L.jpart = c.take<double>((size_t)blocks_max(z));
-  L.upart = c.take<long long>((size_t)blocks_max(z));
+  L.upart = c.take<long long>((size_t)blocks_max(z) * 2);
   L.labels_ws = z.need_labels_ws;
   L.labels = c.take<int32_t>(z.need_labels_ws ? (size_t)z.n : 0);
   L.bytes = c.off;
@@ -247,7 +259,7 @@ bool prof_on() {
 struct StageResult {
   int32_t iters = 0, converged = 0, empty = 0;
   double J = 0.0, shift = 0.0;
-  int64_t uncertain = 0;
+  int64_t uncertain = 0, pairs = 0;
 };
 
 // One stage's Lloyd loop on `rows` rows of Y.
@@ -262,8 +274,9 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
   if (prof)
     for (int32_t i = 0; i < 3 * max_iter; ++i) ev.push_back(take_event());
   HIP_TRY(stage_reset(b.st, s));
-  HIP_TRY(max_abs(b.X, b.dtype, rows * b.d, b.st, s));
+  HIP_TRY(row_stats(b.X, b.dtype, rows, b.d, b.st, s));
   HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, s));
+  HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * b.k * (b.d + 1), s));
   while (launched < max_iter) {
     const int32_t q = std::min(chunk, max_iter - launched);
     for (int32_t i = 0; i < q; ++i) {
@@ -287,6 +300,7 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
   out->J = hs.J;
   out->shift = hs.shift;
   out->uncertain = hs.uncertain;
+  out->pairs = hs.pairs;
   if (prof) {
     // only the first hs.iter passes ran; later ones returned at once
     double a = 0.0, p = 0.0;
@@ -374,8 +388,9 @@ static bool fit_sizes(int64_t n, int32_t d, int32_t k, double f, const km_option
   z->sample = !(opt->skip_stage1 && opt->init_centers);
   z->hist_len = opt->max_iter[0] + opt->max_iter[1];
   const size_t lds = device_lds_limit();
-  z->p1 = plan_pass(z->m, d, k, lds);
-  z->p2 = plan_pass(n, d, k, lds);
+  const int dt = opt->dtype == KM_F32 ? 0 : 1;
+  z->p1 = plan_pass(z->m, d, k, dt, lds, device_cus());
+  z->p2 = plan_pass(n, d, k, dt, lds, device_cus());
   z->need_labels_ws = !labels_given && ((z->stage1 && !z->p1.fused) || !z->p2.fused);
   return true;
 }
@@ -434,8 +449,7 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
   b.cnorm = at<double>(base, L.cnorm);
   b.shiftj = at<double>(base, L.shiftj);
   b.emptyj = at<int32_t>(base, L.emptyj);
-  b.part = at<long long>(base, L.part);
-  b.part2 = at<long long>(base, L.part2);
+  b.slots = at<long long>(base, L.slots);
   b.Jpart = at<double>(base, L.jpart);
   b.upart = at<long long>(base, L.upart);
   b.st = st;
@@ -522,6 +536,7 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
     info->shift[1] = r2.shift;
     info->dist_evals = (int64_t)k * (z.m * r1.iters + n * r2.iters) + (int64_t)k * n;
     info->uncertain = r1.uncertain + hs.uncertain;
+    info->fp64_pairs = r1.pairs + hs.pairs;
     info->seconds[0] = t1 - t0;
     info->seconds[1] = t2 - t1;
     info->seconds[2] = t3 - t2;
@@ -590,16 +605,16 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   if (precision == KM_PREC_BF16_RERANK)
     return fail(KM_EINVAL, "the BF16 MFMA precision path is not available in this build");
   hipStream_t s = (hipStream_t)stream;
-  const PassPlan p = plan_pass(n, d, k, device_lds_limit());
+  const PassPlan p = plan_pass(n, d, k, dtype == KM_F32 ? 0 : 1, device_lds_limit(), device_cus());
   const bool lab_ws = !labels && !p.fused;
   Carver c;
   const size_t C_ = (size_t)k * (d + 1);
   const size_t o_c64 = c.take<double>((size_t)k * d), o_cw = c.take<float>((size_t)k * d),
                o_cn = c.take<float>(k), o_cnorm = c.take<double>(k),
                o_sh = c.take<double>(k), o_em = c.take<int32_t>(k),
-               o_st = c.take<PassState>(1), o_part = c.take<long long>((size_t)p.part_rows * C_),
-               o_part2 = c.take<long long>(32 * C_), o_jp = c.take<double>((size_t)p.blocks),
-               o_up = c.take<long long>((size_t)p.blocks),
+               o_st = c.take<PassState>(1), o_slots = c.take<long long>((size_t)kSlots * C_),
+               o_jp = c.take<double>((size_t)p.blocks),
+               o_up = c.take<long long>((size_t)p.blocks * 2),
                o_lab = c.take<int32_t>(lab_ws ? (size_t)n : 0);
   DevMem mem;
   km_status rc = mem.get(c.off, nullptr, 0, s);
@@ -618,8 +633,7 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   b.cnorm = at<double>(base, o_cnorm);
   b.shiftj = at<double>(base, o_sh);
   b.emptyj = at<int32_t>(base, o_em);
-  b.part = at<long long>(base, o_part);
-  b.part2 = at<long long>(base, o_part2);
+  b.slots = at<long long>(base, o_slots);
   b.Jpart = at<double>(base, o_jp);
   b.upart = at<long long>(base, o_up);
   b.labels = labels ? labels : (lab_ws ? at<int32_t>(base, o_lab) : nullptr);
@@ -629,8 +643,9 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   HIP_TRY(hipMemcpyAsync(b.c64, C, sizeof(double) * k * d, hipMemcpyDeviceToDevice, s));
   HIP_TRY(prep_centers(b.c64, k, d, b.cw, b.cn, b.cnorm, s));
   HIP_TRY(stage_reset(b.st, s));
-  HIP_TRY(max_abs(X, b.dtype, n * d, b.st, s));
+  HIP_TRY(row_stats(X, b.dtype, n, d, b.st, s));
   HIP_TRY(stage_begin(b.st, 1, 0.0, n, b.cnorm, k, s));
+  HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * k * (d + 1), s));
   HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (hs.nonfinite) return fail(KM_EINVAL, "X contains NaN or Inf");

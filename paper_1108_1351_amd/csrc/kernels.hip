@@ -307,6 +307,7 @@ hipError_t centers_from_rows(const void* X, int64_t nrows, int dtype, int32_t d,
 
 __global__ void k_stage_reset(PassState* st) {
   st->maxabs_bits = 0u;
+  st->ticket = 0u;
   st->done = 0;
 }
 
@@ -315,32 +316,42 @@ hipError_t stage_reset(PassState* st, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Per stage: max |x| over the rows (NaN/Inf show as bits >= 0x7f800000).
 template <typename T>
-__global__ __launch_bounds__(256) void k_max_abs(const T* __restrict__ X, int64_t count,
-                                                 PassState* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_row_stats(const T* __restrict__ X, int64_t count,
+                                                   PassState* __restrict__ st) {
   uint32_t mx = 0u;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
-    uint32_t b = __float_as_uint(widen<T>(X[e])) & 0x7fffffffu;  // |x|; NaN/Inf >= 0x7f800000
-    mx = max(mx, b);
-  }
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
+    mx = max(mx, __float_as_uint(widen<T>(X[e])) & 0x7fffffffu);
   for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o));
   __shared__ uint32_t w[4];
   if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t v = max(max(w[0], w[1]), max(w[2], w[3]));
-    atomicMax(&st->maxabs_bits, v);
-  }
+  if (threadIdx.x == 0) atomicMax(&st->maxabs_bits, max(max(w[0], w[1]), max(w[2], w[3])));
 }
 
-hipError_t max_abs(const void* X, int dtype, int64_t count, PassState* st, hipStream_t s) {
+hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
+                     hipStream_t s) {
+  const int64_t count = rows * d;
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 4096));
   if (dtype == 0)
-    hipLaunchKernelGGL(k_max_abs<float>, dim3(g), dim3(256), 0, s, (const float*)X, count, st);
+    hipLaunchKernelGGL(k_row_stats<float>, dim3(g), dim3(256), 0, s, (const float*)X, count, st);
   else
-    hipLaunchKernelGGL(k_max_abs<uint16_t>, dim3(g), dim3(256), 0, s, (const uint16_t*)X,
-                       count, st);
+    hipLaunchKernelGGL(k_row_stats<uint16_t>, dim3(g), dim3(256), 0, s, (const uint16_t*)X, count,
+                       st);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_zero_i64(long long* __restrict__ p, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
+    p[e] = 0;
+}
+
+hipError_t zero_i64(long long* p, int64_t count, hipStream_t s) {
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_zero_i64, dim3(g), dim3(256), 0, s, p, count);
   return hipGetLastError();
 }
 
@@ -402,6 +413,7 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
     st->F = F;
     st->scale = ldexpf(1.0f, F);
     st->cmax = (float)(red[0] * (1.0 + 0x1p-20)) * (1.0f + 0x1p-20f);
+    st->ticket = 0u;
     st->max_iter = max_iter;
     st->tol = tol;
     st->iter = 0;
@@ -411,6 +423,7 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
     st->J = 0.0;
     st->shift = 0.0;
     st->uncertain = 0;
+    st->pairs = 0;
     st->rows = rows;
   }
 }
@@ -559,8 +572,8 @@ __device__ __forceinline__ void assign_tile(
     const T* __restrict__ X, int64_t n, int d, int k, int64_t base, const float* __restrict__ cw,
     const float* __restrict__ cn, const double* __restrict__ c64, float* __restrict__ w,
     float* __restrict__ cnl, int ktile, float cmax, float scale,
-    unsigned long long* __restrict__ S, unsigned int* __restrict__ N,
-    int32_t* __restrict__ labels, double& Jacc, int64_t& ucnt) {
+    unsigned long long* __restrict__ S, int32_t* __restrict__ labels, double& Jacc,
+    int64_t& ucnt) {
   float x[P][DMAX];
   int64_t ip[P];
   bool valid[P];
@@ -621,29 +634,45 @@ __device__ __forceinline__ void assign_tile(
       for (int t = 0; t < DMAX; ++t) {
         if (t < d) {
           const long long q = (long long)__float2int_rn(x[p][t] * scale);
-          atomicAdd(&S[(int64_t)l * d + t], (unsigned long long)q);
+          atomicAdd(&S[(int64_t)l * (d + 1) + t], (unsigned long long)q);
         }
       }
-      atomicAdd(&N[l], 1u);
+      atomicAdd(&S[(int64_t)l * (d + 1) + d], 1ull);
     }
   }
 }
 
-// Fixed-order block sum of J (FP64) and the uncertain count.  256 threads.
-__device__ __forceinline__ void block_sum_J(double Jacc, int64_t ucnt, double* Jpart,
-                                            long long* upart) {
+// Adds a block's LDS cluster sums S [k][d+1] (counts in the last column; the
+// padded row also spreads rows over LDS banks) into slot row blockIdx.x %
+// kSlots with 64-bit integer atomics, whose result does not depend on their
+// order.
+__device__ __forceinline__ void flush_sums(const unsigned long long* __restrict__ S, int k,
+                                           int d, long long* __restrict__ slots) {
+  unsigned long long* row = reinterpret_cast<unsigned long long*>(
+      slots + (int64_t)(blockIdx.x % kSlots) * k * (d + 1));
+  for (int e = threadIdx.x; e < k * (d + 1); e += blockDim.x) {
+    const unsigned long long v = S[e];
+    if (v) atomicAdd(&row[e], v);
+  }
+}
+
+// Fixed-order block sum of J (FP64) and of the FP64-check counts (full checks
+// and pair decisions; both wave-uniform).  256 threads.
+__device__ __forceinline__ void block_sum_J(double Jacc, int64_t ucnt, int64_t pcnt,
+                                            double* Jpart, long long* upart) {
   __shared__ double wJ[4];
-  __shared__ long long wU[4];
+  __shared__ long long wU[4], wP[4];
   for (int o = 32; o > 0; o >>= 1) Jacc += __shfl_xor(Jacc, o);
-  // the fallback count is already wave-uniform
   if ((threadIdx.x & 63) == 0) {
     wJ[threadIdx.x >> 6] = Jacc;
     wU[threadIdx.x >> 6] = ucnt;
+    wP[threadIdx.x >> 6] = pcnt;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     Jpart[blockIdx.x] = ((wJ[0] + wJ[1]) + wJ[2]) + wJ[3];
-    upart[blockIdx.x] = wU[0] + wU[1] + wU[2] + wU[3];
+    upart[2 * blockIdx.x] = wU[0] + wU[1] + wU[2] + wU[3];
+    upart[2 * blockIdx.x + 1] = wP[0] + wP[1] + wP[2] + wP[3];
   }
 }
 
@@ -653,7 +682,7 @@ template <typename T, int DMAX, int P>
 __global__ __launch_bounds__(256) void k_fused(
     const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cw,
     const float* __restrict__ cn, const double* __restrict__ c64, const PassState* __restrict__ st,
-    const int32_t* __restrict__ gate, int update, long long* __restrict__ part,
+    const int32_t* __restrict__ gate, int update, long long* __restrict__ slots,
     double* __restrict__ Jpart, long long* __restrict__ upart, int32_t* __restrict__ labels) {
   if (gated(gate)) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -661,35 +690,24 @@ __global__ __launch_bounds__(256) void k_fused(
   float* cnl = w + (size_t)k * DMAX;
   unsigned long long* S =
       reinterpret_cast<unsigned long long*>(smem + (((size_t)k * DMAX + k) * 4 + 15) / 16 * 16);
-  unsigned int* N = reinterpret_cast<unsigned int*>(S + (size_t)k * d);
   for (int e = threadIdx.x; e < k * DMAX; e += 256) {
     const int j = e / DMAX, t = e - j * DMAX;
     w[e] = t < d ? -2.f * cw[(int64_t)j * d + t] : 0.f;
   }
   for (int j = threadIdx.x; j < k; j += 256) cnl[j] = cn[j];
-  if (update) {
-    for (int e = threadIdx.x; e < k * d; e += 256) S[e] = 0ull;
-    for (int j = threadIdx.x; j < k; j += 256) N[j] = 0u;
-  }
+  if (update)
+    for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
   __syncthreads();
   const float scale = st->scale, cmax = st->cmax;
   double Jacc = 0.0;
-  int64_t ucnt = 0;
+  int64_t ucnt = 0, pcnt = 0;
   const int64_t tile = 256 * P;
   for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile)
     assign_tile<T, DMAX, P, false>(X, n, d, k, base, cw, cn, c64, w, cnl, k, cmax, scale,
-                                   update ? S : nullptr, update ? N : nullptr, labels, Jacc,
-                                   ucnt);
+                                   update ? S : nullptr, labels, Jacc, ucnt);
   __syncthreads();
-  if (update) {
-    long long* pb = part + (int64_t)blockIdx.x * k * (d + 1);
-    for (int e = threadIdx.x; e < k * d; e += 256) {
-      const int j = e / d, t = e - j * d;
-      pb[(int64_t)j * (d + 1) + t] = (long long)S[e];
-    }
-    for (int j = threadIdx.x; j < k; j += 256) pb[(int64_t)j * (d + 1) + d] = (long long)N[j];
-  }
-  block_sum_J(Jacc, ucnt, Jpart, upart);
+  if (update) flush_sums(S, k, d, slots);
+  block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
 }
 
 // Assignment only, centers streamed through LDS by tiles; writes labels.
@@ -705,12 +723,12 @@ __global__ __launch_bounds__(256) void k_assign_tiled(
   float* cnl = w + (size_t)ktile * DMAX;
   const float cmax = st->cmax;
   double Jacc = 0.0;
-  int64_t ucnt = 0;
+  int64_t ucnt = 0, pcnt = 0;
   const int64_t tile = 256 * P;
   for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile)
     assign_tile<T, DMAX, P, true>(X, n, d, k, base, cw, cn, c64, w, cnl, ktile, cmax, 1.f,
-                                  nullptr, nullptr, labels, Jacc, ucnt);
-  block_sum_J(Jacc, ucnt, Jpart, upart);
+                                  nullptr, labels, Jacc, ucnt);
+  block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
 }
 
 // Rows with d above the largest register tile: one point per thread, the row
@@ -725,7 +743,7 @@ __global__ __launch_bounds__(256) void k_assign_generic(
   const float cmax = st->cmax;
   const float Kd = (float)(d + 2) * 0x1p-24f * 1.001f;
   double Jacc = 0.0;
-  int64_t ucnt = 0;
+  int64_t ucnt = 0, pcnt = 0;
   for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
     const int64_t i = base + threadIdx.x;
     const bool valid = i < n;
@@ -756,7 +774,7 @@ __global__ __launch_bounds__(256) void k_assign_generic(
       labels[i] = bi;
     }
   }
-  block_sum_J(Jacc, ucnt, Jpart, upart);
+  block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
 }
 
 // Cluster sums from labels for k*d too large for one LDS array: block (b, s, r)
@@ -766,7 +784,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_update_split(
     const T* __restrict__ X, const int32_t* __restrict__ labels, int64_t n, int d, int k,
     int slice, int crange, const PassState* __restrict__ st, const int32_t* __restrict__ gate,
-    long long* __restrict__ part) {
+    long long* __restrict__ slots) {
   if (gated(gate)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const int t0 = blockIdx.y * slice, tw = min(slice, d - t0);
@@ -790,105 +808,353 @@ __global__ __launch_bounds__(256) void k_update_split(
     if (counts) atomicAdd(&N[l], 1u);
   }
   __syncthreads();
-  long long* pb = part + (int64_t)blockIdx.x * k * (d + 1);
+  unsigned long long* row = reinterpret_cast<unsigned long long*>(
+      slots + (int64_t)(blockIdx.x % kSlots) * k * (d + 1));
   for (int e = threadIdx.x; e < jw * tw; e += 256) {
     const int jj = e / tw, tt = e - jj * tw;
-    pb[(int64_t)(j0 + jj) * (d + 1) + t0 + tt] = (long long)S[(int64_t)jj * slice + tt];
+    const unsigned long long v = S[(int64_t)jj * slice + tt];
+    if (v) atomicAdd(&row[(int64_t)(j0 + jj) * (d + 1) + t0 + tt], v);
   }
   if (counts)
     for (int jj = threadIdx.x; jj < jw; jj += 256)
-      pb[(int64_t)(j0 + jj) * (d + 1) + d] = (long long)N[jj];
+      if (N[jj]) atomicAdd(&row[(int64_t)(j0 + jj) * (d + 1) + d], (unsigned long long)N[jj]);
 }
 
 // ============================================================================
-// Reduction of the block sums, new centers, stage bookkeeping
+// Fused pass on MFMA: x.c^T as 32x32x2 FP32 tiles
 // ============================================================================
-// part2[r][c] = sum over rows b = r, r+R, ... of part[b][c] (exact integer sums).
-__global__ __launch_bounds__(256) void k_reduce_part(const long long* __restrict__ part,
-                                                     int64_t rows, int64_t C, int R,
-                                                     const int32_t* __restrict__ gate,
-                                                     long long* __restrict__ part2) {
-  if (gated(gate)) return;
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int r = blockIdx.y;
-  if (c >= C) return;
-  long long s = 0;
-  for (int64_t b = r; b < rows; b += R) s += part[b * C + c];
-  part2[(int64_t)r * C + c] = s;
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int med3_i32(int a, int b, int c) {
+  return max(min(a, b), min(max(a, b), c));
 }
 
-// One wave per center: exact sums, new center (the average; an empty cluster
-// keeps its center), its movement and norm.
-__global__ __launch_bounds__(64) void k_finalize(
-    const long long* __restrict__ part2, int R, int k, int d, const PassState* __restrict__ st,
-    const int32_t* __restrict__ gate, double* __restrict__ c64, float* __restrict__ cw,
-    float* __restrict__ cn, double* __restrict__ cnorm, double* __restrict__ shiftj,
-    int32_t* __restrict__ emptyj, double* __restrict__ S_out, int64_t* __restrict__ N_out) {
-  if (gated(gate)) return;
-  const int j = blockIdx.x, lane = threadIdx.x;
-  const int64_t C = (int64_t)k * (d + 1);
-  const long long* col = part2 + (int64_t)j * (d + 1);
-  long long Nj = 0;
-  for (int r = 0; r < R; ++r) Nj += col[(int64_t)r * C + d];
-  const int F = st->F;
-  double sh = 0.0, nn = 0.0;
-  for (int t = lane; t < d; t += 64) {
-    long long Sj = 0;
-    for (int r = 0; r < R; ++r) Sj += col[(int64_t)r * C + t];
-    const double sum = ldexp((double)Sj, -F);
-    const double cold = c64[(int64_t)j * d + t];
-    const double cnew = Nj > 0 ? sum / (double)Nj : cold;
-    const double diff = cnew - cold;
-    sh += diff * diff;
-    nn += cnew * cnew;
-    c64[(int64_t)j * d + t] = cnew;
-    cw[(int64_t)j * d + t] = (float)cnew;
-    if (S_out) S_out[(int64_t)j * d + t] = sum;
+// Dims [h*H, h*H + H) of a row into registers; zero beyond d and for invalid rows.
+template <typename T, int H>
+__device__ __forceinline__ void load_half(const T* __restrict__ row, int d, int h, bool valid,
+                                          float (&x)[H]) {
+  const int t0 = h * H;
+#pragma unroll
+  for (int q = 0; q < H; ++q) x[q] = 0.f;
+  if (!valid) return;
+  const T* p = row + t0;
+  const bool full = t0 + H <= d;
+  const uintptr_t ad = reinterpret_cast<uintptr_t>(p);
+  if constexpr (sizeof(T) == 4 && H % 4 == 0) {
+    if (full && (ad & 15u) == 0) {
+#pragma unroll
+      for (int q = 0; q < H; q += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p + q);
+        x[q] = v.x; x[q + 1] = v.y; x[q + 2] = v.z; x[q + 3] = v.w;
+      }
+      return;
+    }
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    sh += __shfl_xor(sh, o);
-    nn += __shfl_xor(nn, o);
+  if constexpr (sizeof(T) == 4 && H == 2) {
+    if (full && (ad & 7u) == 0) {
+      const float2 v = *reinterpret_cast<const float2*>(p);
+      x[0] = v.x; x[1] = v.y;
+      return;
+    }
   }
-  if (lane == 0) {
-    shiftj[j] = sqrt(sh);
-    cn[j] = (float)nn;
-    cnorm[j] = sqrt(nn);
-    emptyj[j] = Nj == 0 ? 1 : 0;
-    if (N_out) N_out[j] = (int64_t)Nj;
+  if constexpr (sizeof(T) == 2 && H % 8 == 0) {
+    if (full && (ad & 15u) == 0) {
+#pragma unroll
+      for (int q = 0; q < H; q += 8) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p + q);
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          x[q + 2 * u] = __uint_as_float(w4[u] << 16);
+          x[q + 2 * u + 1] = __uint_as_float(w4[u] & 0xffff0000u);
+        }
+      }
+      return;
+    }
   }
+#pragma unroll
+  for (int q = 0; q < H; ++q)
+    if (t0 + q < d) x[q] = widen<T>(p[q]);
 }
 
-// One block: J (fixed-order FP64 sum of the block partials), largest movement,
-// empties, bound on ||c||, pass count and the stop decision.
-__global__ __launch_bounds__(256) void k_conclude(
-    PassState* __restrict__ st, const double* __restrict__ Jpart,
-    const long long* __restrict__ upart, int64_t nb, const double* __restrict__ shiftj,
-    const double* __restrict__ cnorm, const int32_t* __restrict__ emptyj, int k, int update,
-    double* __restrict__ J_hist, double* __restrict__ shift_hist) {
-  if (update && st->done) return;
+// FP64 check of the uncertain points of a 32-point MFMA tile.  Every lane of
+// the wave calls this; point p's row sits in registers x of lanes p (dims
+// [0, H)) and p + 32 (dims [H, 2H)), the FP64 centers in LDS (row stride d+1).
+// Each lane takes centers lane, lane + 64, ...; the wave then reduces (D, j)
+// to the smallest D, lowest j on ties.  The squared distance is the plain
+// direct form summed over t = 0..d-1.
+template <int H>
+__device__ __forceinline__ int64_t mfma_fp64_check(bool unc, const float (&x)[H], int d, int k,
+                                                   const double* __restrict__ cs, int& label) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long m = __ballot(unc);
+  const int64_t cnt = __popcll(m);
+  while (m) {
+    const int src = __ffsll((long long)m) - 1;
+    m &= m - 1ull;
+    float xv[2 * H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      xv[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[q]), src));
+      xv[H + q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[q]), src + 32));
+    }
+    double bD = INFINITY;
+    int bj = INT_MAX;
+    for (int j = lane; j < k; j += 64) {
+      const double* cj = cs + (int64_t)j * (d + 1);
+      double D = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2 * H; ++t) {
+        if (t < d) {
+          const double diff = (double)xv[t] - cj[t];
+          D = D + diff * diff;
+        }
+      }
+      if (D < bD) { bD = D; bj = j; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double oD = __shfl_xor(bD, o);
+      const int oj = __shfl_xor(bj, o);
+      if (oD < bD || (oD == bD && oj < bj)) { bD = oD; bj = oj; }
+    }
+    if (lane == src) label = bj < k ? bj : 0;
+  }
+  return cnt;
+}
+
+// Fused pass for d <= 32 and k <= 128.  A wave takes 32 points at a time; for
+// each tile of 32 centers one chain of 32x32x2 MFMAs gives every lane 16
+// squared distances ||x||^2 + ||c||^2 - 2 x.c of its point (lane and lane^32
+// hold the two halves of the 32 centers; the last K=2 step adds ||x||^2 and
+// ||c||^2).  The best two are kept as integer keys (distance bits with the
+// center index in the low bits, so one min3/med3 ranks value and index
+// together); a rigorous error bound certifies the best center or sends the
+// point to the FP64 check.  Cluster sums go to LDS, then to the slots.
+template <typename T, int KD, int NT>
+__global__ __launch_bounds__(256) void k_fused_mfma(
+    const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cw,
+    const float* __restrict__ cn, const double* __restrict__ c64, const PassState* __restrict__ st,
+    const int32_t* __restrict__ gate, int update, long long* __restrict__ slots,
+    double* __restrict__ Jpart, long long* __restrict__ upart, int32_t* __restrict__ labels) {
+  if (gated(gate)) return;
+  constexpr int H = KD / 2;
+  constexpr int BL = NT == 1 ? 4 : (NT == 2 ? 5 : 6);  // bits of a lane-local index (16*NT values)
+  constexpr int BG = BL + 1;                            // bits of a center index (32*NT centers)
+  constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* cs = reinterpret_cast<double*>(smem);  // [k][d+1] FP64 centers
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * (d + 1));
+  const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < k * d; e += 256) {
+    const int j = e / d, t = e - j * d;
+    cs[(int64_t)j * (d + 1) + t] = c64[e];
+  }
+  if (update)
+    for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
+  const float cmax = st->cmax, scale = st->scale;
+  // A operand of step q for center tile t: -2 c[32t + pc][h*H + q]; the extra
+  // step pairs (1, ||c||^2) of the center with (||x||^2, 1) of the point.
+  float a[NT][H], an[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = 32 * t + pc;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      const int dim = h * H + q;
+      a[t][q] = (j < k && dim < d) ? -2.f * cw[(int64_t)j * d + dim] : 0.f;
+    }
+    an[t] = h == 0 ? 1.f : (j < k ? cn[j] : 1e30f);
+  }
+  __syncthreads();
+  // error bound of a distance: (KD + H + 6) u (||x|| + ||c||)^2; keys drop BG bits
+  const float KE = (float)(KD + H + 6) * 0x1p-24f * 1.01f;
+  const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
+  double Jacc = 0.0;
+  int64_t ucnt = 0, pcnt = 0;
+  const int64_t ntile = (n + 31) >> 5;
+  const int64_t tstride = (int64_t)gridDim.x * 4;
+  int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  float xnext[H];
+  {
+    const int64_t i0 = (tile << 5) + pc;
+    load_half<T, H>(X + (i0 < n ? i0 : 0) * d, d, h, tile < ntile && i0 < n, xnext);
+  }
+  for (; tile < ntile; tile += tstride) {
+    const int64_t i = (tile << 5) + pc;
+    const bool valid = i < n;
+    float x[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) x[q] = xnext[q];
+    {  // rows of this wave's next tile, loaded while this one computes
+      const int64_t in = ((tile + tstride) << 5) + pc;
+      load_half<T, H>(X + (in < n ? in : 0) * d, d, h, tile + tstride < ntile && in < n, xnext);
+    }
+    float xs = 0.f;
+#pragma unroll
+    for (int q = 0; q < H; ++q) xs = __builtin_fmaf(x[q], x[q], xs);
+    const float xn2 = xs + __shfl_xor(xs, 32);
+    const float bx = h == 0 ? xn2 : 1.f;
+    int m1 = INT_MAX, m2 = INT_MAX, m3 = INT_MAX;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      v16f acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(an[t], bx, acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < H; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t][q], x[q], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        // the value part drops BG bits already here: the later switch from the
+        // lane-local index l to the center index j (monotone in l within a lane
+        // half) then cannot reorder keys whose value parts are equal
+        const int kv = (__float_as_int(acc[r]) & ~GM) | (16 * t + r);
+        m3 = med3_i32(m2, kv, m3);
+        m2 = med3_i32(m1, kv, m2);
+        m1 = min(m1, kv);
+      }
+    }
+    // lane-local index -> center index, then merge the two halves of the centers
+    auto glob = [&](int key) {
+      const int l = key & LM;
+      return (key & ~GM) | (32 * (l >> 4) + 8 * ((l & 15) >> 2) + 4 * h + (l & 3));
+    };
+    int g1 = glob(m1), g2 = glob(m2), g3 = glob(m3);
+    {
+      const int o1 = __shfl_xor(g1, 32), o2 = __shfl_xor(g2, 32), o3 = __shfl_xor(g3, 32);
+      const int ov[3] = {o1, o2, o3};
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        g3 = med3_i32(g2, ov[u], g3);
+        g2 = med3_i32(g1, ov[u], g2);
+        g1 = min(g1, ov[u]);
+      }
+    }
+    int bi = g1 & GM;
+    const int b2 = g2 & GM;
+    const float v1 = __int_as_float(g1 & ~GM), v2 = __int_as_float(g2 & ~GM),
+                v3 = __int_as_float(g3 & ~GM);
+    const float xn = sqrtf(xn2) * 1.0001f + cmax;
+    const float E2 = 2.f * (KE * xn * xn + 1e-30f);
+    // certain: the best beats every other center; pair: the best is one of the best two
+    const bool certain = k == 1 || (bi < k && (v2 - v1) > E2 + delta * (fabsf(v2) + fabsf(v1)));
+    const bool pair = valid && !certain && bi < k && b2 < k &&
+                      (k == 2 || (v3 - v1) > E2 + delta * (fabsf(v3) + fabsf(v1)));
+    const bool full = valid && !certain && !pair;
+    if (bi >= k) bi = 0;
+    // FP64 squared distance to the best candidate (J), direct form, this lane's dims
+    double p1 = 0.0;
+    {
+      const double* c1 = cs + (int64_t)bi * (d + 1) + h * H;
+#pragma unroll
+      for (int q = 0; q < H; ++q)
+        if (h * H + q < d) {
+          const double e = (double)x[q] - c1[q];
+          p1 = __builtin_fma(e, e, p1);
+        }
+    }
+    double D1 = p1 + __shfl_xor(p1, 32);
+    if (__ballot(pair)) {
+      // the second candidate's FP64 distance decides the pair (lowest index on ties)
+      const double* c2 = cs + (int64_t)(pair ? b2 : 0) * (d + 1) + h * H;
+      double p2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < H; ++q)
+        if (h * H + q < d) {
+          const double e = (double)x[q] - c2[q];
+          p2 = __builtin_fma(e, e, p2);
+        }
+      const double D2 = p2 + __shfl_xor(p2, 32);
+      if (pair && (D2 < D1 || (D2 == D1 && b2 < bi))) {
+        bi = b2;
+        D1 = D2;
+      }
+      pcnt += __popcll(__ballot(pair && h == 0));
+    }
+    if (__ballot(full)) {
+      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi);
+      const int bfull = __shfl(bi, pc);
+      if (full) {
+        bi = bfull < k ? bfull : 0;
+        const double* c1 = cs + (int64_t)bi * (d + 1) + h * H;
+        p1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < H; ++q)
+          if (h * H + q < d) {
+            const double e = (double)x[q] - c1[q];
+            p1 = __builtin_fma(e, e, p1);
+          }
+      }
+      const double pf = p1 + __shfl_xor(p1, 32);
+      if (full) D1 = pf;
+    }
+    if (valid) {
+      if (h == 0) {
+        Jacc += D1;
+        if (labels) labels[i] = bi;
+      }
+      if (update) {
+        unsigned long long* Sr = S + (int64_t)bi * (d + 1);
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+          const int dim = h * H + q;
+          if (dim < d) {
+            const int qv = __float2int_rn(x[q] * scale);
+            atomicAdd(&Sr[dim], (unsigned long long)(long long)qv);
+          }
+        }
+        if (h == 0) atomicAdd(&Sr[d], 1ull);
+      }
+    }
+  }
+  __syncthreads();
+  if (update) flush_sums(S, k, d, slots);
+  block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
+}
+
+// ============================================================================
+// New centers from the slot sums, stage bookkeeping
+// ============================================================================
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long ld_agent(const long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Fixed-order sums of J and the uncertain counts over the assignment blocks,
+// and (when update) the largest movement, the largest ||c|| and the empties.
+__device__ void conclude_block(PassState* __restrict__ st, const double* __restrict__ Jpart,
+                               const long long* __restrict__ upart, int64_t nb,
+                               const double* __restrict__ shiftj, const double* __restrict__ cnorm,
+                               const int32_t* __restrict__ emptyj, int k, bool update,
+                               double* __restrict__ J_hist, double* __restrict__ shift_hist) {
   __shared__ double rJ[256], rS[256], rN[256];
-  __shared__ long long rU[256], rE[256];
+  __shared__ long long rU[256], rE[256], rP[256];
   const int tid = threadIdx.x;
-  double J = 0.0;
-  long long U = 0;
+  double J = 0.0, sh = 0.0, nm = 0.0;
+  long long U = 0, E = 0, Pc = 0;
   for (int64_t b = tid; b < nb; b += 256) {
-    J += Jpart[b];
-    U += upart[b];
+    J += ld_agent(&Jpart[b]);
+    U += ld_agent(&upart[2 * b]);
+    Pc += ld_agent(&upart[2 * b + 1]);
   }
-  double sh = 0.0, nm = 0.0;
-  long long E = 0;
   if (update)
     for (int j = tid; j < k; j += 256) {
-      sh = fmax(sh, shiftj[j]);
-      nm = fmax(nm, cnorm[j]);
-      E += emptyj[j];
+      sh = fmax(sh, ld_agent(&shiftj[j]));
+      nm = fmax(nm, ld_agent(&cnorm[j]));
+      E += ld_agent(&emptyj[j]);
     }
-  rJ[tid] = J; rU[tid] = U; rS[tid] = sh; rN[tid] = nm; rE[tid] = E;
+  rJ[tid] = J; rU[tid] = U; rS[tid] = sh; rN[tid] = nm; rE[tid] = E; rP[tid] = Pc;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (tid < o) {
       rJ[tid] += rJ[tid + o];
       rU[tid] += rU[tid + o];
+      rP[tid] += rP[tid + o];
       rS[tid] = fmax(rS[tid], rS[tid + o]);
       rN[tid] = fmax(rN[tid], rN[tid + o]);
       rE[tid] += rE[tid + o];
@@ -898,6 +1164,7 @@ __global__ __launch_bounds__(256) void k_conclude(
   if (tid == 0) {
     st->J = rJ[0];
     st->uncertain += rU[0];
+    st->pairs += rP[0];
     if (update) {
       const int it = st->iter;
       st->shift = rS[0];
@@ -910,6 +1177,98 @@ __global__ __launch_bounds__(256) void k_conclude(
       st->done = (st->converged || it + 1 >= st->max_iter) ? 1 : 0;
     }
   }
+}
+
+// One block per center: the exact sum of its kSlots slot rows (zeroed for the
+// next pass), the new center (the average; an empty cluster keeps its center),
+// its movement and norm.  The last block to finish concludes the pass.
+__global__ __launch_bounds__(256) void k_finalize(
+    long long* __restrict__ slots, int k, int d, PassState* __restrict__ st,
+    const int32_t* __restrict__ gate, double* __restrict__ c64, float* __restrict__ cw,
+    float* __restrict__ cn, double* __restrict__ cnorm, double* __restrict__ shiftj,
+    int32_t* __restrict__ emptyj, double* __restrict__ S_out, int64_t* __restrict__ N_out,
+    const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
+    double* __restrict__ J_hist, double* __restrict__ shift_hist) {
+  if (gated(gate)) return;
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int64_t C = (int64_t)k * (d + 1);
+  long long* col = slots + (int64_t)j * (d + 1);
+  __shared__ long long red[256];
+  __shared__ double rd[256], rn[256];
+  __shared__ int last;
+  long long v = 0;
+  if (tid < kSlots) {
+    v = col[(int64_t)tid * C + d];
+    col[(int64_t)tid * C + d] = 0;
+  }
+  red[tid] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  const long long Nj = red[0];
+  __syncthreads();
+  const int F = st->F;
+  double sh = 0.0, nn = 0.0;
+  const int r = tid & 31, c = tid >> 5;  // 32 slots x 8 dims per round
+  for (int t0 = 0; t0 < d; t0 += 8) {
+    const int t = t0 + c;
+    long long sv = 0;
+    if (t < d) {
+      sv = col[(int64_t)r * C + t];
+      col[(int64_t)r * C + t] = 0;
+    }
+    red[tid] = sv;
+    __syncthreads();
+    for (int o = 16; o > 0; o >>= 1) {
+      if (r < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (r == 0 && t < d) {
+      const double sum = ldexp((double)red[tid], -F);
+      const double cold = c64[(int64_t)j * d + t];
+      const double cnew = Nj > 0 ? sum / (double)Nj : cold;
+      const double diff = cnew - cold;
+      sh += diff * diff;
+      nn += cnew * cnew;
+      c64[(int64_t)j * d + t] = cnew;
+      cw[(int64_t)j * d + t] = (float)cnew;
+      if (S_out) S_out[(int64_t)j * d + t] = sum;
+    }
+    __syncthreads();
+  }
+  rd[tid] = sh;
+  rn[tid] = nn;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      rd[tid] += rd[tid + o];
+      rn[tid] += rn[tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    shiftj[j] = sqrt(rd[0]);
+    cn[j] = (float)rn[0];
+    cnorm[j] = sqrt(rn[0]);
+    emptyj[j] = Nj == 0 ? 1 : 0;
+    if (N_out) N_out[j] = (int64_t)Nj;
+    __threadfence();
+    last = atomicAdd(&st->ticket, 1u) == (unsigned)(k - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  conclude_block(st, Jpart, upart, nb, shiftj, cnorm, emptyj, k, true, J_hist, shift_hist);
+  if (tid == 0) st->ticket = 0u;
+}
+
+// J and uncertain counts of a labelling pass (no update).  One block.
+__global__ __launch_bounds__(256) void k_sum_J(PassState* __restrict__ st,
+                                               const double* __restrict__ Jpart,
+                                               const long long* __restrict__ upart, int64_t nb) {
+  conclude_block(st, Jpart, upart, nb, nullptr, nullptr, nullptr, 0, false, nullptr, nullptr);
 }
 
 // ============================================================================
@@ -933,96 +1292,149 @@ static int pick_ppt(int dmax) {
   return 1;
 }
 
-PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, size_t lds_limit) {
+// Calls f with the kernel instance for the plan (function pointer).
+template <typename T, int KD, typename F>
+static void visit_mfma_nt(int nt, F&& f) {
+  switch (nt) {
+    case 1: f(k_fused_mfma<T, KD, 1>); break;
+    case 2: f(k_fused_mfma<T, KD, 2>); break;
+    case 3: f(k_fused_mfma<T, KD, 3>); break;
+    default: f(k_fused_mfma<T, KD, 4>); break;
+  }
+}
+
+template <typename T, typename F>
+static void visit_mfma(int kd, int nt, F&& f) {
+  switch (kd) {
+    case 2: visit_mfma_nt<T, 2>(nt, f); break;
+    case 4: visit_mfma_nt<T, 4>(nt, f); break;
+    case 8: visit_mfma_nt<T, 8>(nt, f); break;
+    case 16: visit_mfma_nt<T, 16>(nt, f); break;
+    default: visit_mfma_nt<T, 32>(nt, f); break;
+  }
+}
+
+template <typename T, typename F>
+static void visit_fused(int dmax, F&& f) {
+  switch (dmax) {
+    case 2: f(k_fused<T, 2, 4>); break;
+    case 4: f(k_fused<T, 4, 4>); break;
+    case 8: f(k_fused<T, 8, 4>); break;
+    case 16: f(k_fused<T, 16, 2>); break;
+    case 32: f(k_fused<T, 32, 1>); break;
+    case 64: f(k_fused<T, 64, 1>); break;
+    default: f(k_fused<T, 128, 1>); break;
+  }
+}
+
+template <typename T, typename F>
+static void visit_tiled(int dmax, F&& f) {
+  switch (dmax) {
+    case 2: f(k_assign_tiled<T, 2, 4>); break;
+    case 4: f(k_assign_tiled<T, 4, 4>); break;
+    case 8: f(k_assign_tiled<T, 8, 4>); break;
+    case 16: f(k_assign_tiled<T, 16, 2>); break;
+    case 32: f(k_assign_tiled<T, 32, 1>); break;
+    case 64: f(k_assign_tiled<T, 64, 1>); break;
+    default: f(k_assign_tiled<T, 128, 1>); break;
+  }
+}
+
+// Resident blocks of 256 threads per CU for a kernel with `lds` bytes of dynamic LDS.
+template <typename K>
+static int64_t resident_blocks(K kernel, size_t lds, int cus) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, lds) != hipSuccess || nb < 1)
+    nb = 1;
+  return (int64_t)nb * std::max(1, cus);
+}
+
+template <typename T>
+static int64_t plan_blocks(const PassPlan& p, int cus) {
+  int64_t r = 0;
+  auto f = [&](auto kern) { r = resident_blocks(kern, p.lds_assign, cus); };
+  if (p.mfma) visit_mfma<T>(p.kd, p.nt, f);
+  else if (p.fused) visit_fused<T>(p.dmax, f);
+  else if (p.dmax) visit_tiled<T>(p.dmax, f);
+  else r = resident_blocks(k_assign_generic<T>, 0, cus);
+  return r;
+}
+
+PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, size_t lds_limit, int cus) {
   PassPlan p{};
   p.dmax = pick_dmax(d);
   p.ppt = pick_ppt(p.dmax);
   const size_t budget = std::min<size_t>(lds_limit, 65536);
   const size_t kk = (size_t)k, dd = (size_t)d;
-  const size_t lds_fused =
-      ((kk * (size_t)p.dmax + kk) * 4 + 15) / 16 * 16 + kk * dd * 8 + kk * 4;
-  p.fused = p.dmax != 0 && lds_fused <= budget;
-  const int64_t tile_pts = 256LL * p.ppt;
-  const int64_t tiles = std::max<int64_t>(1, (rows + tile_pts - 1) / tile_pts);
-  const int64_t C = (int64_t)k * (d + 1);
-  const int64_t cap_rows = std::max<int64_t>(16, (256LL << 20) / (C * 8));  // part <= 256 MB
-  if (p.fused) {
-    p.lds_assign = lds_fused;
-    p.blocks = std::min<int64_t>(std::min<int64_t>(tiles, 2048), cap_rows);
-    p.part_rows = p.blocks;
-    p.ktile = k;
-    return p;
-  }
-  if (p.dmax) {
-    p.ktile = (int)std::max<int64_t>(1, std::min<int64_t>(k, 8192 / p.dmax));
-    p.lds_assign = (size_t)p.ktile * p.dmax * 4 + (size_t)p.ktile * 4;
-  }
-  p.blocks = std::min<int64_t>(tiles, 2048);
-  // split update: crange centers x slice dims of 64-bit sums + crange counts in LDS
-  int crange = k, slice;
-  if (kk * 12 > budget) {
-    crange = (int)(budget / 12);
-    slice = 1;
+  // MFMA fused pass: d <= 32, k <= 128, LDS for FP64 centers + sums + counts
+  const size_t lds_mfma = kk * (dd + 1) * 8 * 2;
+  const size_t lds_fused = ((kk * (size_t)p.dmax + kk) * 4 + 15) / 16 * 16 + kk * (dd + 1) * 8;
+  int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
+  if (d <= 32 && k <= 128 && lds_mfma <= budget) {
+    p.mfma = true;
+    p.fused = true;
+    p.kd = p.dmax;
+    p.nt = (k + 31) / 32;
+    p.lds_assign = lds_mfma;
+    work = ((rows + 31) / 32 + 3) / 4;
   } else {
-    slice = (int)std::min<size_t>(dd, (budget - kk * 4) / (kk * 8));
+    p.fused = p.dmax != 0 && lds_fused <= budget;
+    const int64_t tile_pts = 256LL * p.ppt;
+    work = (rows + tile_pts - 1) / tile_pts;
+    if (p.fused) {
+      p.lds_assign = lds_fused;
+      p.ktile = k;
+    } else {
+      if (p.dmax) {
+        p.ktile = (int)std::max<int64_t>(1, std::min<int64_t>(k, 8192 / p.dmax));
+        p.lds_assign = (size_t)p.ktile * p.dmax * 4 + (size_t)p.ktile * 4;
+      }
+      // split update: crange centers x slice dims of 64-bit sums + crange counts in LDS
+      int crange = k, slice;
+      if (kk * 12 > budget) {
+        crange = (int)(budget / 12);
+        slice = 1;
+      } else {
+        slice = (int)std::min<size_t>(dd, (budget - kk * 4) / (kk * 8));
+      }
+      p.crange = crange;
+      p.slice = std::max(1, slice);
+      p.nslices = (d + p.slice - 1) / p.slice;
+      p.lds_update = (size_t)crange * p.slice * 8 + (size_t)crange * 4;
+      p.ublocks = std::max<int64_t>(1, std::min<int64_t>((rows + 2047) / 2048, 1024));
+    }
   }
-  p.crange = crange;
-  p.slice = std::max(1, slice);
-  p.nslices = (d + p.slice - 1) / p.slice;
-  p.lds_update = (size_t)crange * p.slice * 8 + (size_t)crange * 4;
-  p.ublocks = std::min<int64_t>(std::min<int64_t>((rows + 2047) / 2048, 1024), cap_rows);
-  p.ublocks = std::max<int64_t>(1, p.ublocks);
-  p.part_rows = p.ublocks;
+  // a persistent grid: no more blocks than stay resident at once
+  const int64_t res = dtype == 0 ? plan_blocks<float>(p, cus) : plan_blocks<uint16_t>(p, cus);
+  p.blocks = std::max<int64_t>(1, std::min<int64_t>({work, res, (int64_t)kMaxBlocks}));
   return p;
-}
-
-template <typename T, int DMAX, int P>
-static void launch_fused(const PassBufs& b, const PassPlan& p, bool update, const int32_t* gate,
-                         hipStream_t s) {
-  hipLaunchKernelGGL((k_fused<T, DMAX, P>), dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
-                     (const T*)b.X, b.n, b.d, b.k, b.cw, b.cn, b.c64, (const PassState*)b.st,
-                     gate, update ? 1 : 0, b.part, b.Jpart, b.upart, b.labels);
-}
-
-template <typename T, int DMAX, int P>
-static void launch_tiled(const PassBufs& b, const PassPlan& p, const int32_t* gate,
-                         hipStream_t s) {
-  hipLaunchKernelGGL((k_assign_tiled<T, DMAX, P>), dim3((unsigned)p.blocks), dim3(256),
-                     p.lds_assign, s, (const T*)b.X, b.n, b.d, b.k, p.ktile, b.cw, b.cn, b.c64,
-                     (const PassState*)b.st, gate, b.Jpart, b.upart, b.labels);
 }
 
 template <typename T>
 static void dispatch_fused(const PassBufs& b, const PassPlan& p, bool update,
                            const int32_t* gate, hipStream_t s) {
-  switch (p.dmax) {
-    case 2: launch_fused<T, 2, 4>(b, p, update, gate, s); break;
-    case 4: launch_fused<T, 4, 4>(b, p, update, gate, s); break;
-    case 8: launch_fused<T, 8, 4>(b, p, update, gate, s); break;
-    case 16: launch_fused<T, 16, 2>(b, p, update, gate, s); break;
-    case 32: launch_fused<T, 32, 1>(b, p, update, gate, s); break;
-    case 64: launch_fused<T, 64, 1>(b, p, update, gate, s); break;
-    case 128: launch_fused<T, 128, 1>(b, p, update, gate, s); break;
-    default: break;
-  }
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s, (const T*)b.X,
+                       b.n, b.d, b.k, b.cw, b.cn, b.c64, (const PassState*)b.st, gate,
+                       update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
+  };
+  if (p.mfma) visit_mfma<T>(p.kd, p.nt, launch);
+  else visit_fused<T>(p.dmax, launch);
 }
 
 template <typename T>
 static void dispatch_tiled(const PassBufs& b, const PassPlan& p, const int32_t* gate,
                            hipStream_t s) {
-  switch (p.dmax) {
-    case 2: launch_tiled<T, 2, 4>(b, p, gate, s); break;
-    case 4: launch_tiled<T, 4, 4>(b, p, gate, s); break;
-    case 8: launch_tiled<T, 8, 4>(b, p, gate, s); break;
-    case 16: launch_tiled<T, 16, 2>(b, p, gate, s); break;
-    case 32: launch_tiled<T, 32, 1>(b, p, gate, s); break;
-    case 64: launch_tiled<T, 64, 1>(b, p, gate, s); break;
-    case 128: launch_tiled<T, 128, 1>(b, p, gate, s); break;
-    default:
-      hipLaunchKernelGGL(k_assign_generic<T>, dim3((unsigned)p.blocks), dim3(256), 0, s,
-                         (const T*)b.X, b.n, b.d, b.k, b.cw, b.cn, b.c64,
+  if (p.dmax) {
+    visit_tiled<T>(p.dmax, [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
+                         (const T*)b.X, b.n, b.d, b.k, p.ktile, b.cw, b.cn, b.c64,
                          (const PassState*)b.st, gate, b.Jpart, b.upart, b.labels);
-      break;
+    });
+  } else {
+    hipLaunchKernelGGL(k_assign_generic<T>, dim3((unsigned)p.blocks), dim3(256), 0, s,
+                       (const T*)b.X, b.n, b.d, b.k, b.cw, b.cn, b.c64, (const PassState*)b.st,
+                       gate, b.Jpart, b.upart, b.labels);
   }
 }
 
@@ -1034,26 +1446,11 @@ static void split_update(const PassBufs& b, const PassPlan& p, const int32_t* ga
   if (b.dtype == 0)
     hipLaunchKernelGGL(k_update_split<float>, grid, dim3(256), p.lds_update, s,
                        (const float*)b.X, (const int32_t*)b.labels, b.n, b.d, b.k, p.slice,
-                       crange, (const PassState*)b.st, gate, b.part);
+                       crange, (const PassState*)b.st, gate, b.slots);
   else
     hipLaunchKernelGGL(k_update_split<uint16_t>, grid, dim3(256), p.lds_update, s,
                        (const uint16_t*)b.X, (const int32_t*)b.labels, b.n, b.d, b.k, p.slice,
-                       crange, (const PassState*)b.st, gate, b.part);
-}
-
-static void reduce_finalize_conclude(const PassBufs& b, const PassPlan& p, const int32_t* gate,
-                                     hipStream_t s) {
-  const int64_t C = (int64_t)b.k * (b.d + 1);
-  const int R = (int)std::min<int64_t>(p.part_rows, 32);
-  hipLaunchKernelGGL(k_reduce_part, dim3((unsigned)((C + 255) / 256), (unsigned)R), dim3(256), 0,
-                     s, (const long long*)b.part, p.part_rows, C, R, gate, b.part2);
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(64), 0, s, (const long long*)b.part2,
-                     R, b.k, b.d, (const PassState*)b.st, gate, b.c64, b.cw, b.cn, b.cnorm,
-                     b.shiftj, b.emptyj, b.S_out, b.N_out);
-  hipLaunchKernelGGL(k_conclude, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
-                     (const long long*)b.upart, p.blocks, (const double*)b.shiftj,
-                     (const double*)b.cnorm, (const int32_t*)b.emptyj, b.k, 1, b.J_hist,
-                     b.shift_hist);
+                       crange, (const PassState*)b.st, gate, b.slots);
 }
 
 hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
@@ -1072,12 +1469,13 @@ hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStrea
   const int32_t* gate = update ? &b.st->done : nullptr;
   if (update) {
     if (!p.fused) split_update(b, p, gate, s);
-    reduce_finalize_conclude(b, p, gate, s);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(256), 0, s, b.slots, b.k, b.d, b.st,
+                       gate, b.c64, b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out,
+                       (const double*)b.Jpart, (const long long*)b.upart, p.blocks, b.J_hist,
+                       b.shift_hist);
   } else {
-    hipLaunchKernelGGL(k_conclude, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
-                       (const long long*)b.upart, p.blocks, (const double*)b.shiftj,
-                       (const double*)b.cnorm, (const int32_t*)b.emptyj, b.k, 0, nullptr,
-                       nullptr);
+    hipLaunchKernelGGL(k_sum_J, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
+                       (const long long*)b.upart, p.blocks);
   }
   return hipGetLastError();
 }

@@ -10,6 +10,8 @@ constexpr int kSelDigitBits = 12;
 constexpr int kSelBins = 1 << kSelDigitBits;
 constexpr int64_t kSelChunk = 8192;   // indices per block in the ordered compaction
 constexpr int kThreads = 256;          // threads per block of the point kernels
+constexpr int kSlots = 32;             // rows of 64-bit cluster-sum slots blocks add into
+constexpr int kMaxBlocks = 4096;       // upper bound of an assignment kernel's grid
 
 // Progress of one radix selection of the r smallest 64-bit keys.  When done,
 // a key is selected iff its top `bits` bits are <= prefix (keys are distinct).
@@ -30,13 +32,15 @@ struct PassState {
   float scale;         // 2^F
   float cmax;          // upper bound of max_j ||c_j||, for the FP32 error bound
   uint32_t maxabs_bits;  // bits of max |x| over the stage's rows (NaN/Inf -> >= 0x7f800000)
+  uint32_t ticket;     // blocks of the finalize kernel that are done (last one concludes)
   int32_t nonfinite;
   int32_t empty;
   int32_t converged;
   double tol;
   double J;
   double shift;
-  int64_t uncertain;   // labels settled by the FP64 check, cumulative over the stage
+  int64_t uncertain;   // labels settled by the FP64 check over all centers, cumulative
+  int64_t pairs;       // labels settled by FP64 between the best two candidates, cumulative
   int64_t rows;
 };
 
@@ -51,7 +55,9 @@ hipError_t gather_rows(const void* X, int64_t nrows, int dtype, int32_t d, const
 hipError_t centers_from_rows(const void* X, int64_t nrows, int dtype, int32_t d,
                              const int64_t* idx, int32_t k, double* c64, hipStream_t s);
 hipError_t stage_reset(PassState* st, hipStream_t s);
-hipError_t max_abs(const void* X, int dtype, int64_t count, PassState* st, hipStream_t s);
+hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
+                     hipStream_t s);
+hipError_t zero_i64(long long* p, int64_t count, hipStream_t s);
 hipError_t prep_centers(const double* c64, int32_t k, int32_t d, float* cw, float* cn,
                         double* cnorm, hipStream_t s);
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
@@ -61,7 +67,8 @@ struct PassBufs {
   const void* X; int dtype; int64_t n; int32_t d; int32_t k;
   double* c64; float* cw; float* cn; double* cnorm;
   double* shiftj; int32_t* emptyj;
-  long long* part; long long* part2; double* Jpart; long long* upart;
+  long long* slots;    // [kSlots][k][d+1] exact cluster sums (counts last); zero between passes
+  double* Jpart; long long* upart;
   int32_t* labels;     // labels of the rows (required by the split path)
   PassState* st;
   double* J_hist; double* shift_hist;
@@ -70,6 +77,8 @@ struct PassBufs {
 
 // Geometry chosen once per (rows, d, k): fused or split path and block counts.
 struct PassPlan {
+  bool mfma;         // fused pass on FP32 MFMA (x.c^T as 32x32x2 tiles)
+  int kd, nt;        // padded dims and 32-center tiles of the MFMA kernel
   bool fused;
   int dmax;          // register tile of a row (0: generic)
   int ppt;           // points per thread
@@ -78,12 +87,11 @@ struct PassPlan {
   int slice;         // dims per slice of the split update
   int nslices;
   int crange;        // centers per range of the split update
-  int64_t part_rows; // rows of `part`
   size_t lds_assign, lds_update;
   int ktile;         // centers per LDS tile (split assign)
 };
 
-PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, size_t lds_limit);
+PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, size_t lds_limit, int cus);
 hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
 // the assignment kernel of a pass, and everything after it (update, reduction, stop test)
 hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);

@@ -246,3 +246,27 @@ def test_full_size_16d_sampled_outputs():
     assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
     if info["converged"][1]:
         assert ref.shift < w.tol * 1.01
+
+
+@pytest.mark.parametrize("d,k", [(16, 64), (4, 32), (2, 8), (32, 100)])
+def test_near_duplicate_centers_resolved_in_fp64(d, k):
+    """Pairs of centers closer than the FP32 score quantum (but far above the
+    1e-6 near-tie exemption): the FP64 decision must match the oracle on every
+    point, including candidates held by the same lane half."""
+    rng = np.random.default_rng(d * 31 + k)
+    base = rng.uniform(-40, 40, size=(k // 2, d))
+    off = rng.normal(size=(k // 2, d))
+    off *= 2e-3 / np.linalg.norm(off, axis=1, keepdims=True)
+    C = np.empty((k, d))
+    C[0::2][:len(base)] = base
+    C[1::2][:len(base)] = base + off
+    if k % 2:
+        C[-1] = rng.uniform(-40, 40, size=d)
+    comp = rng.integers(0, k, size=40_000)
+    Xh = (C[comp] + rng.normal(0, 1.0, size=(40_000, d))).astype(np.float32)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    lab = out["labels"].cpu().numpy()
+    ex = exempt_mask(Xh, C)
+    assert np.array_equal(lab[~ex], ref.labels[~ex])
+    assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
