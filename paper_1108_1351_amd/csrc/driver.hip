@@ -105,7 +105,7 @@ struct Carver {
 
 struct Layout {
   size_t sel, hist, blk, sub, init_sel, init_key, xs, c64, cw, cn, cnorm, shiftj, emptyj, st,
-      jh, sh, slots, jpart, upart, labels;
+      jh, sh, slots, qslots, jc, cb16, cnb, queue, qthr, jpart, upart, labels;
   size_t bytes;
   bool labels_ws;
 };
@@ -120,7 +120,14 @@ struct Sizes {
   bool need_labels_ws;
 };
 
-int64_t blocks_max(const Sizes& z) { return std::max(z.stage1 ? z.p1.blocks : 0, z.p2.blocks); }
+// per-block partials: the BF16 screen's re-screen kernel has a second set
+int64_t blocks_max(const Sizes& z) {
+  auto nb = [](const PassPlan& p) { return p.bf16 ? 2 * p.blocks : p.blocks; };
+  return std::max(z.stage1 ? nb(z.p1) : 0, nb(z.p2));
+}
+
+bool any_bf16(const Sizes& z) { return (z.stage1 && z.p1.bf16) || z.p2.bf16; }
+int ks_max(const Sizes& z) { return std::max(z.stage1 ? z.p1.ks : 0, z.p2.ks); }
 
 Layout make_layout(const Sizes& z) {
   Layout L{};
@@ -144,6 +151,12 @@ Layout make_layout(const Sizes& z) {
   L.sh = c.take<double>((size_t)z.hist_len);
   const size_t C = (size_t)z.k * (z.d + 1);
   L.slots = c.take<long long>((size_t)kSlots * C);
+  L.qslots = c.take<long long>((size_t)kSlots * z.k);
+  L.jc = c.take<double>((size_t)z.k);
+  L.cb16 = c.take<uint16_t>(any_bf16(z) ? (size_t)z.k * 16 * ks_max(z) : 0);
+  L.cnb = c.take<float>((size_t)z.k);
+  L.queue = c.take<int32_t>(any_bf16(z) ? (size_t)z.n : 0);
+  L.qthr = c.take<float>(any_bf16(z) ? (size_t)z.n : 0);
   L.jpart = c.take<double>((size_t)blocks_max(z));
   L.upart = c.take<long long>((size_t)blocks_max(z) * 2);
   L.labels_ws = z.need_labels_ws;
@@ -275,8 +288,11 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
     for (int32_t i = 0; i < 3 * max_iter; ++i) ev.push_back(take_event());
   HIP_TRY(stage_reset(b.st, s));
   HIP_TRY(row_stats(b.X, b.dtype, rows, b.d, b.st, s));
-  HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, s));
+  if (plan.bf16) HIP_TRY(row_norms(b.X, b.dtype, rows, b.d, b.st, s));
+  HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, b.d, s));
+  if (plan.bf16) HIP_TRY(prep_bf16(b.c64, b.k, b.d, plan.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * b.k * (b.d + 1), s));
+  HIP_TRY(zero_i64(b.qslots, (int64_t)kSlots * b.k, s));
   while (launched < max_iter) {
     const int32_t q = std::min(chunk, max_iter - launched);
     for (int32_t i = 0; i < q; ++i) {
@@ -373,8 +389,8 @@ static bool fit_sizes(int64_t n, int32_t d, int32_t k, double f, const km_option
   if (k > n) return !fail(KM_EINVAL, "k (%d) must not exceed n (%lld)", k, (long long)n);
   if (!(f > 0.0 && f <= 1.0)) return !fail(KM_EINVAL, "subset_frac must be in (0, 1]");
   if (opt->dtype != KM_F32 && opt->dtype != KM_BF16) return !fail(KM_EINVAL, "unknown dtype");
-  if (opt->precision == KM_PREC_BF16_RERANK)
-    return !fail(KM_EINVAL, "the BF16 MFMA precision path is not available in this build");
+  if (opt->precision < KM_PREC_AUTO || opt->precision > KM_PREC_BF16_RERANK)
+    return !fail(KM_EINVAL, "unknown precision");
   for (int s = 0; s < 2; ++s) {
     if (opt->max_iter[s] < 1) return !fail(KM_EINVAL, "max_iter must be >= 1");
     if (!(opt->tol[s] >= 0.0)) return !fail(KM_EINVAL, "tol must be >= 0 and not NaN");
@@ -389,8 +405,8 @@ static bool fit_sizes(int64_t n, int32_t d, int32_t k, double f, const km_option
   z->hist_len = opt->max_iter[0] + opt->max_iter[1];
   const size_t lds = device_lds_limit();
   const int dt = opt->dtype == KM_F32 ? 0 : 1;
-  z->p1 = plan_pass(z->m, d, k, dt, lds, device_cus());
-  z->p2 = plan_pass(n, d, k, dt, lds, device_cus());
+  z->p1 = plan_pass(z->m, d, k, dt, (int)opt->precision, lds, device_cus());
+  z->p2 = plan_pass(n, d, k, dt, (int)opt->precision, lds, device_cus());
   z->need_labels_ws = !labels_given && ((z->stage1 && !z->p1.fused) || !z->p2.fused);
   return true;
 }
@@ -450,6 +466,12 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
   b.shiftj = at<double>(base, L.shiftj);
   b.emptyj = at<int32_t>(base, L.emptyj);
   b.slots = at<long long>(base, L.slots);
+  b.qslots = at<long long>(base, L.qslots);
+  b.Jc = at<double>(base, L.jc);
+  b.cb16 = at<uint16_t>(base, L.cb16);
+  b.cnB = at<float>(base, L.cnb);
+  b.queue = at<int32_t>(base, L.queue);
+  b.qthr = at<float>(base, L.qthr);
   b.Jpart = at<double>(base, L.jpart);
   b.upart = at<long long>(base, L.upart);
   b.st = st;
@@ -602,10 +624,11 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   if (!valid_common(n, d, k)) return KM_EINVAL;
   if (!X || !C) return fail(KM_EINVAL, "X and C must not be NULL");
   if (dtype != KM_F32 && dtype != KM_BF16) return fail(KM_EINVAL, "unknown dtype");
-  if (precision == KM_PREC_BF16_RERANK)
-    return fail(KM_EINVAL, "the BF16 MFMA precision path is not available in this build");
+  if (precision < KM_PREC_AUTO || precision > KM_PREC_BF16_RERANK)
+    return fail(KM_EINVAL, "unknown precision");
   hipStream_t s = (hipStream_t)stream;
-  const PassPlan p = plan_pass(n, d, k, dtype == KM_F32 ? 0 : 1, device_lds_limit(), device_cus());
+  const PassPlan p = plan_pass(n, d, k, dtype == KM_F32 ? 0 : 1, (int)precision,
+                               device_lds_limit(), device_cus());
   const bool lab_ws = !labels && !p.fused;
   Carver c;
   const size_t C_ = (size_t)k * (d + 1);
@@ -613,8 +636,12 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
                o_cn = c.take<float>(k), o_cnorm = c.take<double>(k),
                o_sh = c.take<double>(k), o_em = c.take<int32_t>(k),
                o_st = c.take<PassState>(1), o_slots = c.take<long long>((size_t)kSlots * C_),
-               o_jp = c.take<double>((size_t)p.blocks),
-               o_up = c.take<long long>((size_t)p.blocks * 2),
+               o_qs = c.take<long long>((size_t)kSlots * k), o_jc = c.take<double>(k),
+               o_cb = c.take<uint16_t>(p.bf16 ? (size_t)k * 16 * p.ks : 0),
+               o_cnb = c.take<float>(k), o_q = c.take<int32_t>(p.bf16 ? (size_t)n : 0),
+               o_qt = c.take<float>(p.bf16 ? (size_t)n : 0),
+               o_jp = c.take<double>((size_t)p.blocks * 2),
+               o_up = c.take<long long>((size_t)p.blocks * 4),
                o_lab = c.take<int32_t>(lab_ws ? (size_t)n : 0);
   DevMem mem;
   km_status rc = mem.get(c.off, nullptr, 0, s);
@@ -634,6 +661,12 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   b.shiftj = at<double>(base, o_sh);
   b.emptyj = at<int32_t>(base, o_em);
   b.slots = at<long long>(base, o_slots);
+  b.qslots = at<long long>(base, o_qs);
+  b.Jc = at<double>(base, o_jc);
+  b.cb16 = at<uint16_t>(base, o_cb);
+  b.cnB = at<float>(base, o_cnb);
+  b.queue = at<int32_t>(base, o_q);
+  b.qthr = at<float>(base, o_qt);
   b.Jpart = at<double>(base, o_jp);
   b.upart = at<long long>(base, o_up);
   b.labels = labels ? labels : (lab_ws ? at<int32_t>(base, o_lab) : nullptr);
@@ -644,8 +677,11 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   HIP_TRY(prep_centers(b.c64, k, d, b.cw, b.cn, b.cnorm, s));
   HIP_TRY(stage_reset(b.st, s));
   HIP_TRY(row_stats(X, b.dtype, n, d, b.st, s));
-  HIP_TRY(stage_begin(b.st, 1, 0.0, n, b.cnorm, k, s));
+  if (p.bf16) HIP_TRY(row_norms(X, b.dtype, n, d, b.st, s));
+  HIP_TRY(stage_begin(b.st, 1, 0.0, n, b.cnorm, k, d, s));
+  if (p.bf16) HIP_TRY(prep_bf16(b.c64, k, d, p.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * k * (d + 1), s));
+  HIP_TRY(zero_i64(b.qslots, (int64_t)kSlots * k, s));
   HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (hs.nonfinite) return fail(KM_EINVAL, "X contains NaN or Inf");

@@ -50,6 +50,25 @@ __device__ __forceinline__ int64_t shfl_i64(int64_t v, int src) {
 
 __device__ __forceinline__ bool gated(const int32_t* gate) { return gate && *gate; }
 
+// Loads that bypass this CU's cache (other blocks of the kernel wrote them).
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long ld_agent(const long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Round to the nearest BF16 (ties to even); inputs are finite.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+
 // ============================================================================
 // Sampling: the r smallest keys among `count` candidates (indices 0..count-1,
 // or the indices listed in idx_arr), by 12-bit digits from the top.
@@ -307,6 +326,8 @@ hipError_t centers_from_rows(const void* X, int64_t nrows, int dtype, int32_t d,
 
 __global__ void k_stage_reset(PassState* st) {
   st->maxabs_bits = 0u;
+  st->xn2max_bits = 0u;
+  st->qcount = 0u;
   st->ticket = 0u;
   st->done = 0;
 }
@@ -340,6 +361,60 @@ hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, PassStat
   else
     hipLaunchKernelGGL(k_row_stats<uint16_t>, dim3(g), dim3(256), 0, s, (const uint16_t*)X, count,
                        st);
+  return hipGetLastError();
+}
+
+// Max ||x||^2 over the rows (thread per row; rows of 16 bytes loaded at once
+// when aligned).  Needed by the BF16 screen only.
+template <typename T>
+__global__ __launch_bounds__(256) void k_row_norms(const T* __restrict__ X, int64_t rows, int d,
+                                                   PassState* __restrict__ st) {
+  float xn2 = 0.f;
+  constexpr int V = 16 / sizeof(T);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += stride) {
+    const T* xr = X + i * d;
+    float s2 = 0.f;
+    int t = 0;
+    if ((reinterpret_cast<uintptr_t>(xr) & 15u) == 0) {
+      for (; t + V <= d; t += V) {
+        const uint4 v = *reinterpret_cast<const uint4*>(xr + t);
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if constexpr (sizeof(T) == 4) {
+            const float f = __uint_as_float(w4[u]);
+            s2 = __builtin_fmaf(f, f, s2);
+          } else {
+            const float f0 = __uint_as_float(w4[u] << 16), f1 = __uint_as_float(w4[u] & 0xffff0000u);
+            s2 = __builtin_fmaf(f0, f0, s2);
+            s2 = __builtin_fmaf(f1, f1, s2);
+          }
+        }
+      }
+    }
+    for (; t < d; ++t) {
+      const float f = widen<T>(xr[t]);
+      s2 = __builtin_fmaf(f, f, s2);
+    }
+    xn2 = fmaxf(xn2, s2);
+  }
+  for (int o = 32; o > 0; o >>= 1) xn2 = fmaxf(xn2, __shfl_xor(xn2, o));
+  __shared__ float wn[4];
+  if ((threadIdx.x & 63) == 0) wn[threadIdx.x >> 6] = xn2;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(&st->xn2max_bits, __float_as_uint(fmaxf(fmaxf(wn[0], wn[1]), fmaxf(wn[2], wn[3]))));
+}
+
+hipError_t row_norms(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
+                     hipStream_t s) {
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + 255) / 256, 8192));
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_row_norms<float>, dim3(g), dim3(256), 0, s, (const float*)X, rows, d, st);
+  else
+    hipLaunchKernelGGL(k_row_norms<uint16_t>, dim3(g), dim3(256), 0, s, (const uint16_t*)X, rows,
+                       d, st);
   return hipGetLastError();
 }
 
@@ -390,7 +465,7 @@ __device__ __forceinline__ int ceil_log2(int64_t v) {
 __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
                                                      int32_t max_iter, double tol, int64_t rows,
                                                      const double* __restrict__ cnorm,
-                                                     int32_t k) {
+                                                     int32_t k, int32_t d_) {
   __shared__ double red[256];
   double m = 0.0;
   for (int j = threadIdx.x; j < k; j += 256) m = fmax(m, cnorm[j]);
@@ -412,6 +487,20 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
     }
     st->F = F;
     st->scale = ldexpf(1.0f, F);
+    // the FP32 sum of squares of a row is within d * 2^-24 <= 2^-16 (d <= 256) of
+    // ||x||^2, so xm bounds every row's squared norm
+    const float xm = __uint_as_float(st->xn2max_bits) * (1.0f + 0x1p-10f);
+    // squared norms of row slices add as rint(q * 2^FQ): a row's parts sum to at
+    // most 2^(61 - ceil_log2(rows)) (plus a half per slice), so rows of them stay
+    // below 2^62
+    int FQ = 0;
+    if (st->xn2max_bits != 0u && !st->nonfinite) {
+      FQ = 60 - ilogbf(xm) - ceil_log2(rows);
+      FQ = min(200, max(-200, FQ));
+    }
+    st->FQ = FQ;
+    st->B = xm;
+    st->qcount = 0u;
     st->cmax = (float)(red[0] * (1.0 + 0x1p-20)) * (1.0f + 0x1p-20f);
     st->ticket = 0u;
     st->max_iter = max_iter;
@@ -429,8 +518,9 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
 }
 
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
-                       const double* cnorm, int32_t k, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(256), 0, s, st, max_iter, tol, rows, cnorm, k);
+                       const double* cnorm, int32_t k, int32_t d, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(256), 0, s, st, max_iter, tol, rows, cnorm, k,
+                     d);
   return hipGetLastError();
 }
 
@@ -618,16 +708,18 @@ __device__ __forceinline__ void assign_tile(
   for (int p = 0; p < P; ++p) {
     if (!valid[p]) continue;
     const int l = bi[p];
-    const double* cl = c64 + (int64_t)l * d;
-    double D = 0.0;
+    {
+      const double* cl = c64 + (int64_t)l * d;
+      double D = 0.0;
 #pragma unroll
-    for (int t = 0; t < DMAX; ++t) {
-      if (t < d) {
-        const double diff = (double)x[p][t] - cl[t];
-        D = D + diff * diff;
+      for (int t = 0; t < DMAX; ++t) {
+        if (t < d) {
+          const double diff = (double)x[p][t] - cl[t];
+          D = D + diff * diff;
+        }
       }
+      Jacc += D;
     }
-    Jacc += D;
     if (labels) labels[ip[p]] = l;
     if (S) {
 #pragma unroll
@@ -770,8 +862,14 @@ __global__ __launch_bounds__(256) void k_assign_generic(
     const bool unc = valid && k > 1 && !((sec - best) > 2.f * E);
     ucnt += wave_fp64_fallback<T>(unc, i, X, d, k, c64, bi);
     if (valid) {
-      Jacc += dist64_row<T>(xr, c64 + (int64_t)bi * d, d);
       labels[i] = bi;
+      const double* cl = c64 + (int64_t)bi * d;
+      double D = 0.0;
+      for (int t = 0; t < d; ++t) {
+        const double diff = (double)widen<T>(xr[t]) - cl[t];
+        D = D + diff * diff;
+      }
+      Jacc += D;
     }
   }
   block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
@@ -779,45 +877,59 @@ __global__ __launch_bounds__(256) void k_assign_generic(
 
 // Cluster sums from labels for k*d too large for one LDS array: block (b, s, r)
 // adds dims [s*slice, ...) of the points of block b whose label lies in
-// center range r into LDS, then writes them to row b of `part`.
+// center range r into LDS, then into the slots.  With qslots it also adds the
+// slice's part of every point's squared norm, rint(sum x^2 * 2^FQ), so that J
+// follows exactly from the cluster sums.
 template <typename T>
 __global__ __launch_bounds__(256) void k_update_split(
     const T* __restrict__ X, const int32_t* __restrict__ labels, int64_t n, int d, int k,
     int slice, int crange, const PassState* __restrict__ st, const int32_t* __restrict__ gate,
-    long long* __restrict__ slots) {
+    long long* __restrict__ slots, long long* __restrict__ qslots) {
   if (gated(gate)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const int t0 = blockIdx.y * slice, tw = min(slice, d - t0);
   const int j0 = blockIdx.z * crange, jw = min(crange, k - j0);
   unsigned long long* S = reinterpret_cast<unsigned long long*>(smem);
-  unsigned int* N = reinterpret_cast<unsigned int*>(S + (size_t)crange * slice);
+  unsigned long long* Q = S + (size_t)crange * slice;
+  unsigned int* N = reinterpret_cast<unsigned int*>(Q + crange);
   for (int e = threadIdx.x; e < jw * slice; e += 256) S[e] = 0ull;
-  for (int j = threadIdx.x; j < jw; j += 256) N[j] = 0u;
+  for (int j = threadIdx.x; j < jw; j += 256) {
+    Q[j] = 0ull;
+    N[j] = 0u;
+  }
   __syncthreads();
   const float scale = st->scale;
+  const double scaleQ = ldexp(1.0, st->FQ);
   const bool counts = blockIdx.y == 0;
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const int l = labels[i] - j0;
     if (l < 0 || l >= jw) continue;
     const T* xr = X + i * d + t0;
+    double q2 = 0.0;
     for (int tt = 0; tt < tw; ++tt) {
-      const long long q = (long long)__float2int_rn(widen<T>(xr[tt]) * scale);
+      const float v = widen<T>(xr[tt]);
+      const long long q = (long long)__float2int_rn(v * scale);
       atomicAdd(&S[(int64_t)l * slice + tt], (unsigned long long)q);
+      q2 = __builtin_fma((double)v, (double)v, q2);
     }
+    if (qslots) atomicAdd(&Q[l], (unsigned long long)__double2ll_rn(q2 * scaleQ));
     if (counts) atomicAdd(&N[l], 1u);
   }
   __syncthreads();
-  unsigned long long* row = reinterpret_cast<unsigned long long*>(
-      slots + (int64_t)(blockIdx.x % kSlots) * k * (d + 1));
+  const int slot = blockIdx.x % kSlots;
+  unsigned long long* row = reinterpret_cast<unsigned long long*>(slots + (int64_t)slot * k * (d + 1));
   for (int e = threadIdx.x; e < jw * tw; e += 256) {
     const int jj = e / tw, tt = e - jj * tw;
     const unsigned long long v = S[(int64_t)jj * slice + tt];
     if (v) atomicAdd(&row[(int64_t)(j0 + jj) * (d + 1) + t0 + tt], v);
   }
-  if (counts)
-    for (int jj = threadIdx.x; jj < jw; jj += 256)
-      if (N[jj]) atomicAdd(&row[(int64_t)(j0 + jj) * (d + 1) + d], (unsigned long long)N[jj]);
+  for (int jj = threadIdx.x; jj < jw; jj += 256) {
+    if (counts && N[jj])
+      atomicAdd(&row[(int64_t)(j0 + jj) * (d + 1) + d], (unsigned long long)N[jj]);
+    if (qslots && Q[jj])
+      atomicAdd(reinterpret_cast<unsigned long long*>(qslots + (int64_t)slot * k + j0 + jj), Q[jj]);
+  }
 }
 
 // ============================================================================
@@ -1113,23 +1225,341 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
 }
 
 // ============================================================================
-// New centers from the slot sums, stage bookkeeping
+// BF16 screen: x.c^T as 32x32x16 BF16 MFMA tiles, for d in (32, 256] or BF16 data
 // ============================================================================
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ long long ld_agent(const long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Dims [t0, t0+8) of a row as BF16 (zero beyond d and for invalid rows).  BF16
+// data is taken as is; FP32 data is rounded to the nearest BF16.
+template <typename T>
+__device__ __forceinline__ v8bf load8_bf16(const T* __restrict__ row, int t0, int d, bool valid) {
+  u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (valid) {
+    const T* p = row + t0;
+    const bool full = t0 + 8 <= d;
+    if constexpr (sizeof(T) == 2) {
+      if (full && (reinterpret_cast<uintptr_t>(p) & 15u) == 0) {
+        return __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(p));
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (t0 + e < d) b[e] = p[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (t0 + e < d) b[e] = f32_to_bf16(p[e]);
+    }
+  }
+  return __builtin_bit_cast(v8bf, b);
 }
 
-// Fixed-order sums of J and the uncertain counts over the assignment blocks,
-// and (when update) the largest movement, the largest ||c|| and the empties.
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// Among candidate centers cand[0..nc) (wave-uniform loop bound ncmax), the
+// nearest to the lane's point: FP32 direct-form distances first, certified by
+// their error bound; FP64 when the FP32 gap is inside it.  The point's row
+// comes from X (both lane halves compute half the dims; lane h holds dims
+// [h*KH, (h+1)*KH) of each 16-dim step).  Ties go to the lowest index.
+template <typename T, int KS>
+__device__ __forceinline__ int rerank(const T* __restrict__ xr, int d, int h, bool active,
+                                      const int* cand, int nc, int ncmax,
+                                      const float* __restrict__ cw,
+                                      const double* __restrict__ c64, float cmax,
+                                      int64_t& fp64_count) {
+  float best = INFINITY, sec = INFINITY;
+  int bj = INT_MAX;
+  for (int q = 0; q < ncmax; ++q) {
+    const int j = (active && q < nc) ? cand[q] : 0;
+    const float* cj = cw + (int64_t)j * d;
+    float part = 0.f;
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int t = 16 * s + 8 * h + e;
+        if (t < d) {
+          const float diff = widen<T>(xr[t]) - cj[t];
+          part = __builtin_fmaf(diff, diff, part);
+        }
+      }
+    const float D = part + __shfl_xor(part, 32);
+    if (active && q < nc) {
+      if (D < best || (D == best && j < bj)) {
+        sec = best;
+        best = D;
+        bj = j;
+      } else if (D < sec) {
+        sec = D;
+      }
+    }
+  }
+  // FP32 direct form: (KS*8 + 4) u D from the arithmetic, 2 sqrt(D) u ||c|| from
+  // the rounded center
+  const float u = 0x1p-24f * 1.01f;
+  auto err = [&](float D) { return (float)(KS * 8 + 4) * u * D + 2.f * sqrtf(D) * u * cmax + 1e-30f; };
+  const bool sure = nc <= 1 || (sec - best) > err(best) + err(sec);
+  const bool need = active && !sure;
+  if (__ballot(need)) {
+    double b64 = INFINITY;
+    int b64j = INT_MAX;
+    for (int q = 0; q < ncmax; ++q) {
+      const int j = (need && q < nc) ? cand[q] : 0;
+      const double* cj = c64 + (int64_t)j * d;
+      double part = 0.0;
+      for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int t = 16 * s + 8 * h + e;
+          if (t < d) {
+            const double diff = (double)widen<T>(xr[t]) - cj[t];
+            part = __builtin_fma(diff, diff, part);
+          }
+        }
+      const double D = part + __shfl_xor(part, 32);
+      if (need && q < nc && (D < b64 || (D == b64 && j < b64j))) {
+        b64 = D;
+        b64j = j;
+      }
+    }
+    if (need) bj = b64j;
+    fp64_count += __popcll(__ballot(need && h == 0));
+  }
+  return bj;
+}
+
+// MODE 0: the points of X; each lane half keeps the best four keys of its 16
+// scores per center tile (score bits, local index in the low bits), the halves
+// merge, and the point is decided as certain, by a re-rank of the candidates
+// within the error band, or queued for MODE 1 when more than four centers lie
+// in the band.  MODE 1: the queued points; every center whose screened score
+// is within the point's threshold becomes a candidate of the re-rank.
+// 512 threads: 8 waves x PT tiles of 32 points share each center tile in LDS.
+template <typename T, int KS, int PT, int MODE>
+__global__ __launch_bounds__(512) void k_assign_bf16(
+    const T* __restrict__ X, int64_t n, int d, int k, const uint16_t* __restrict__ cb16,
+    const float* __restrict__ cnB, const float* __restrict__ cw, const double* __restrict__ c64,
+    PassState* __restrict__ st, const int32_t* __restrict__ gate, int32_t* __restrict__ labels,
+    int32_t* __restrict__ queue, float* __restrict__ qthr, double* __restrict__ Jpart,
+    long long* __restrict__ upart) {
+  if (gated(gate)) return;
+  constexpr int KD = KS * 16;
+  constexpr int RS = KD + 8;      // LDS row stride in BF16 elements (spreads rows over banks)
+  constexpr int CMAX = 16;        // candidates kept per queued point
+  __shared__ __align__(16) uint16_t ctile[32 * RS];
+  __shared__ float cbias[32];
+  __shared__ int cand_n[MODE == 1 ? 8 * PT * 32 : 1];
+  __shared__ int cand_j[MODE == 1 ? 8 * PT * 32 * CMAX : 512 * 4];
+  const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
+  const int nct = (k + 31) / 32;
+  int BG = 5;
+  while ((1 << BG) < 32 * nct) ++BG;
+  const int GM = (1 << BG) - 1;
+  const float B = st->B, cmax = st->cmax;
+  // screen error: BF16 rounding of the centers (and of FP32 rows), 2^-8 ||x|| ||c||
+  // each, plus the FP32 accumulation of the MFMA chain
+  const float eb = (sizeof(T) == 4 ? 2.f : 1.f) * 0x1p-8f * 1.01f;
+  const float ea = (float)(KD + 8) * 0x1p-24f * 1.01f;
+  const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
+  const int64_t count = MODE == 0 ? n : (int64_t)ld_agent(reinterpret_cast<const int32_t*>(&st->qcount));
+  const int64_t per_block = 8 * PT * 32;
+  int64_t nfull = 0, ncand = 0;
+  for (int64_t base = (int64_t)blockIdx.x * per_block; base < count;
+       base += (int64_t)gridDim.x * per_block) {
+    v8bf x[PT][KS];
+    int64_t ip[PT];
+    bool valid[PT];
+    float xn[PT], thr[PT];
+    int m1[PT], m2[PT], m3[PT], m4[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int64_t e = base + (int64_t)(wave * PT + p) * 32 + pc;
+      valid[p] = e < count;
+      ip[p] = 0;
+      thr[p] = 0.f;
+      if (valid[p]) {
+        ip[p] = MODE == 0 ? e : (int64_t)queue[e];
+        if (MODE == 1) thr[p] = qthr[e];
+      }
+      float s2 = 0.f;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        x[p][s] = load8_bf16<T>(X + ip[p] * d, 16 * s + 8 * h, d, valid[p]);
+        const uint4 w = __builtin_bit_cast(uint4, x[p][s]);
+        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          s2 = __builtin_fmaf(bf16_lo(w4[u]), bf16_lo(w4[u]), s2);
+          s2 = __builtin_fmaf(bf16_hi(w4[u]), bf16_hi(w4[u]), s2);
+        }
+      }
+      xn[p] = sqrtf(s2 + __shfl_xor(s2, 32)) * 1.01f;
+      m1[p] = m2[p] = m3[p] = m4[p] = INT_MAX;
+      if (MODE == 1 && h == 0) cand_n[(wave * PT + p) * 32 + pc] = 0;
+    }
+    for (int ct = 0; ct < nct; ++ct) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < 32 * (KD / 8); e += 512) {
+        const int row = e / (KD / 8), c8 = e - row * (KD / 8);
+        const int j = ct * 32 + row;
+        uint4 v = {0u, 0u, 0u, 0u};
+        if (j < k) v = *reinterpret_cast<const uint4*>(cb16 + (int64_t)j * KD + c8 * 8);
+        *reinterpret_cast<uint4*>(&ctile[row * RS + c8 * 8]) = v;
+      }
+      if (threadIdx.x < 32) {
+        const int j = ct * 32 + threadIdx.x;
+        cbias[threadIdx.x] = j < k ? cnB[j] : 1e30f;
+      }
+      __syncthreads();
+      v16f acc[PT];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float cb = cbias[8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll
+        for (int p = 0; p < PT; ++p) acc[p][r] = cb;
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const v8bf a = *reinterpret_cast<const v8bf*>(&ctile[pc * RS + 16 * s + 8 * h]);
+#pragma unroll
+        for (int p = 0; p < PT; ++p) acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, x[p][s], acc[p], 0, 0, 0);
+      }
+      if constexpr (MODE == 0) {
+        const int lbase = ct << 4;  // local index 16 ct + r, monotone in the center index
+#pragma unroll
+        for (int p = 0; p < PT; ++p)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int kv = (__float_as_int(acc[p][r]) & ~GM) | (lbase + r);
+            m4[p] = med3_i32(m3[p], kv, m4[p]);
+            m3[p] = med3_i32(m2[p], kv, m3[p]);
+            m2[p] = med3_i32(m1[p], kv, m2[p]);
+            m1[p] = min(m1[p], kv);
+          }
+      } else {
+#pragma unroll
+        for (int p = 0; p < PT; ++p)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            if (valid[p] && acc[p][r] <= thr[p]) {
+              const int j = ct * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+              const int slot = (wave * PT + p) * 32 + pc;
+              const int q = atomicAdd(&cand_n[slot], 1);
+              if (q < CMAX && j < k) cand_j[slot * CMAX + q] = j;
+            }
+          }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const float E2 = 2.f * (eb * xn[p] * cmax + ea * (cmax * cmax + B + 2.f * xn[p] * cmax));
+      const int* cand = nullptr;
+      int nc = 0;
+      bool full = false, decided = false;
+      int label = 0;
+      if constexpr (MODE == 0) {
+        // lane-local index -> center index, then merge the two halves
+        int g[4] = {m1[p], m2[p], m3[p], m4[p]};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int l = g[u] & GM;
+          g[u] = (g[u] & ~GM) | (32 * (l >> 4) + 8 * ((l & 15) >> 2) + 4 * h + (l & 3));
+        }
+        int o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o[u] = __shfl_xor(g[u], 32);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          g[3] = med3_i32(g[2], o[u], g[3]);
+          g[2] = med3_i32(g[1], o[u], g[2]);
+          g[1] = med3_i32(g[0], o[u], g[1]);
+          g[0] = min(g[0], o[u]);
+        }
+        float v[4];
+        int jj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v[u] = __int_as_float(g[u] & ~GM);
+          jj[u] = g[u] & GM;
+        }
+        auto apart = [&](float a, float b) {
+          return (b - a) > E2 + delta * (fabsf(a) + fabsf(b));
+        };
+        if (k == 1 || (jj[0] < k && apart(v[0], v[1]))) {
+          decided = true;
+          label = jj[0] < k ? jj[0] : 0;
+        } else if (jj[0] < k && (k <= 4 || apart(v[0], v[3]))) {
+          int* mine = &cand_j[threadIdx.x * 4];
+          mine[nc++] = jj[0];
+#pragma unroll
+          for (int u = 1; u < 4; ++u)
+            if (jj[u] < k && !apart(v[0], v[u])) mine[nc++] = jj[u];
+          cand = mine;
+        } else {
+          full = true;
+        }
+        // queue: every center whose score is within the band of the best
+        const bool q = valid[p] && full && h == 0;
+        const unsigned long long bq = __ballot(q);
+        if (bq) {
+          unsigned base_q = 0;
+          if (lane == 0) base_q = atomicAdd(&st->qcount, (unsigned)__popcll(bq));
+          base_q = __shfl(base_q, 0);
+          if (q) {
+            const unsigned pos = base_q + __popcll(bq & ((1ull << lane) - 1ull));
+            queue[pos] = (int32_t)ip[p];
+            qthr[pos] = v[0] + E2 + 4.f * delta * (fabsf(v[0]) + E2) + 1e-30f;
+          }
+        }
+        nfull += __popcll(bq);
+      } else {
+        const int slot = (wave * PT + p) * 32 + pc;
+        const int cn_ = cand_n[slot];
+        if (cn_ > CMAX) {
+          full = true;  // more candidates than the list holds: FP64 over all centers
+        } else {
+          nc = cn_;
+          cand = &cand_j[slot * CMAX];
+        }
+      }
+      if (!valid[p]) {
+        decided = true;
+        nc = 0;
+      }
+      int ncmax = nc;
+      for (int o = 32; o > 0; o >>= 1) ncmax = max(ncmax, __shfl_xor(ncmax, o));
+      const bool rr = !decided && !full && nc > 0;
+      if (ncmax > 0) {
+        const int lab = rerank<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax,
+                                      ncand);
+        if (rr) label = lab;
+      }
+      if (MODE == 1) {
+        // overflowing lists: all centers in FP64, cooperatively across the wave
+        const bool ovf = valid[p] && full;
+        int lab2 = label;
+        nfull += wave_fp64_fallback<T>(ovf && h == 0, ip[p], X, d, k, c64, lab2);
+        lab2 = __shfl(lab2, pc);
+        if (ovf) label = lab2;
+      }
+      if (valid[p] && h == 0 && (MODE == 1 || !full)) labels[ip[p]] = label < k ? label : 0;
+    }
+  }
+  block_sum_J(0.0, nfull, ncand, Jpart, upart);
+}
+
+// ============================================================================
+// New centers from the slot sums, stage bookkeeping
+// ============================================================================
+// Fixed-order sums of J (the assignment blocks' partials, or the per-cluster
+// values Jc when the split path derives J from the cluster sums), of the FP64
+// check counts, and (when update) the largest movement, the largest ||c|| and
+// the empties; then the pass bookkeeping.
 __device__ void conclude_block(PassState* __restrict__ st, const double* __restrict__ Jpart,
                                const long long* __restrict__ upart, int64_t nb,
-                               const double* __restrict__ shiftj, const double* __restrict__ cnorm,
+                               const double* __restrict__ Jc, const double* __restrict__ shiftj,
+                               const double* __restrict__ cnorm,
                                const int32_t* __restrict__ emptyj, int k, bool update,
                                double* __restrict__ J_hist, double* __restrict__ shift_hist) {
   __shared__ double rJ[256], rS[256], rN[256];
@@ -1138,10 +1568,12 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
   double J = 0.0, sh = 0.0, nm = 0.0;
   long long U = 0, E = 0, Pc = 0;
   for (int64_t b = tid; b < nb; b += 256) {
-    J += ld_agent(&Jpart[b]);
+    if (!Jc) J += ld_agent(&Jpart[b]);
     U += ld_agent(&upart[2 * b]);
     Pc += ld_agent(&upart[2 * b + 1]);
   }
+  if (Jc)
+    for (int j = tid; j < k; j += 256) J += ld_agent(&Jc[j]);
   if (update)
     for (int j = tid; j < k; j += 256) {
       sh = fmax(sh, ld_agent(&shiftj[j]));
@@ -1165,6 +1597,7 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
     st->J = rJ[0];
     st->uncertain += rU[0];
     st->pairs += rP[0];
+    st->qcount = 0u;
     if (update) {
       const int it = st->iter;
       st->shift = rS[0];
@@ -1180,37 +1613,49 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
 }
 
 // One block per center: the exact sum of its kSlots slot rows (zeroed for the
-// next pass), the new center (the average; an empty cluster keeps its center),
-// its movement and norm.  The last block to finish concludes the pass.
+// next pass), then (update) the new center -- the average; an empty cluster
+// keeps its center -- its movement and norm, and the BF16 copy of the screen.
+// With qslots, J of the cluster follows from the sums at the pass's centers:
+// sum ||x - c||^2 = Q - 2 c.S + N ||c||^2.  The last block concludes the pass.
 __global__ __launch_bounds__(256) void k_finalize(
-    long long* __restrict__ slots, int k, int d, PassState* __restrict__ st,
-    const int32_t* __restrict__ gate, double* __restrict__ c64, float* __restrict__ cw,
-    float* __restrict__ cn, double* __restrict__ cnorm, double* __restrict__ shiftj,
-    int32_t* __restrict__ emptyj, double* __restrict__ S_out, int64_t* __restrict__ N_out,
+    long long* __restrict__ slots, long long* __restrict__ qslots, int k, int d,
+    PassState* __restrict__ st, const int32_t* __restrict__ gate, int update,
+    double* __restrict__ c64, float* __restrict__ cw, float* __restrict__ cn,
+    double* __restrict__ cnorm, double* __restrict__ shiftj, int32_t* __restrict__ emptyj,
+    double* __restrict__ S_out, int64_t* __restrict__ N_out, double* __restrict__ Jc,
+    uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
     double* __restrict__ J_hist, double* __restrict__ shift_hist) {
   if (gated(gate)) return;
   const int j = blockIdx.x, tid = threadIdx.x;
   const int64_t C = (int64_t)k * (d + 1);
   long long* col = slots + (int64_t)j * (d + 1);
-  __shared__ long long red[256];
-  __shared__ double rd[256], rn[256];
+  __shared__ long long red[256], redq[256];
+  __shared__ double rd[256], rn[256], rcs[256], rco[256];
   __shared__ int last;
-  long long v = 0;
+  long long v = 0, vq = 0;
   if (tid < kSlots) {
     v = col[(int64_t)tid * C + d];
     col[(int64_t)tid * C + d] = 0;
+    if (qslots) {
+      vq = qslots[(int64_t)tid * k + j];
+      qslots[(int64_t)tid * k + j] = 0;
+    }
   }
   red[tid] = v;
+  redq[tid] = vq;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
+    if (tid < o) {
+      red[tid] += red[tid + o];
+      redq[tid] += redq[tid + o];
+    }
     __syncthreads();
   }
-  const long long Nj = red[0];
+  const long long Nj = red[0], Qj = redq[0];
   __syncthreads();
   const int F = st->F;
-  double sh = 0.0, nn = 0.0;
+  double sh = 0.0, nn = 0.0, csum = 0.0, cold2 = 0.0;
   const int r = tid & 31, c = tid >> 5;  // 32 slots x 8 dims per round
   for (int t0 = 0; t0 < d; t0 += 8) {
     const int t = t0 + c;
@@ -1228,31 +1673,45 @@ __global__ __launch_bounds__(256) void k_finalize(
     if (r == 0 && t < d) {
       const double sum = ldexp((double)red[tid], -F);
       const double cold = c64[(int64_t)j * d + t];
-      const double cnew = Nj > 0 ? sum / (double)Nj : cold;
-      const double diff = cnew - cold;
-      sh += diff * diff;
-      nn += cnew * cnew;
-      c64[(int64_t)j * d + t] = cnew;
-      cw[(int64_t)j * d + t] = (float)cnew;
+      csum += cold * sum;
+      cold2 += cold * cold;
+      if (update) {
+        const double cnew = Nj > 0 ? sum / (double)Nj : cold;
+        const double diff = cnew - cold;
+        sh += diff * diff;
+        nn += cnew * cnew;
+        c64[(int64_t)j * d + t] = cnew;
+        cw[(int64_t)j * d + t] = (float)cnew;
+        if (cb16) cb16[(int64_t)j * kd16 + t] = f32_to_bf16((float)(-2.0 * cnew));
+      }
       if (S_out) S_out[(int64_t)j * d + t] = sum;
     }
     __syncthreads();
   }
   rd[tid] = sh;
   rn[tid] = nn;
+  rcs[tid] = csum;
+  rco[tid] = cold2;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (tid < o) {
       rd[tid] += rd[tid + o];
       rn[tid] += rn[tid + o];
+      rcs[tid] += rcs[tid + o];
+      rco[tid] += rco[tid + o];
     }
     __syncthreads();
   }
   if (tid == 0) {
-    shiftj[j] = sqrt(rd[0]);
-    cn[j] = (float)rn[0];
-    cnorm[j] = sqrt(rn[0]);
-    emptyj[j] = Nj == 0 ? 1 : 0;
+    if (qslots)  // a sum of squares: a negative value is cancellation
+      Jc[j] = fmax(0.0, ldexp((double)Qj, -st->FQ) - 2.0 * rcs[0] + (double)Nj * rco[0]);
+    if (update) {
+      shiftj[j] = sqrt(rd[0]);
+      cn[j] = (float)rn[0];
+      cnorm[j] = sqrt(rn[0]);
+      emptyj[j] = Nj == 0 ? 1 : 0;
+      if (cnB) cnB[j] = (float)(rn[0] + (double)st->B);
+    }
     if (N_out) N_out[j] = (int64_t)Nj;
     __threadfence();
     last = atomicAdd(&st->ticket, 1u) == (unsigned)(k - 1) ? 1 : 0;
@@ -1260,15 +1719,39 @@ __global__ __launch_bounds__(256) void k_finalize(
   __syncthreads();
   if (!last) return;
   __threadfence();
-  conclude_block(st, Jpart, upart, nb, shiftj, cnorm, emptyj, k, true, J_hist, shift_hist);
+  conclude_block(st, Jpart, upart, nb, qslots ? Jc : nullptr, shiftj, cnorm, emptyj, k,
+                 update != 0, J_hist, shift_hist);
   if (tid == 0) st->ticket = 0u;
 }
 
-// J and uncertain counts of a labelling pass (no update).  One block.
+// J and FP64-check counts of a labelling pass of the fused paths.  One block.
 __global__ __launch_bounds__(256) void k_sum_J(PassState* __restrict__ st,
                                                const double* __restrict__ Jpart,
                                                const long long* __restrict__ upart, int64_t nb) {
-  conclude_block(st, Jpart, upart, nb, nullptr, nullptr, nullptr, 0, false, nullptr, nullptr);
+  conclude_block(st, Jpart, upart, nb, nullptr, nullptr, nullptr, nullptr, 0, false, nullptr,
+                 nullptr);
+}
+
+// BF16 copy of -2 c (dims padded with zeros to kd16) and ||c||^2 + B.
+__global__ __launch_bounds__(64) void k_prep_bf16(const double* __restrict__ c64, int k, int d,
+                                                  int kd16, const PassState* __restrict__ st,
+                                                  uint16_t* __restrict__ cb16,
+                                                  float* __restrict__ cnB) {
+  const int j = blockIdx.x, lane = threadIdx.x;
+  double acc = 0.0;
+  for (int t = lane; t < kd16; t += 64) {
+    const double c = t < d ? c64[(int64_t)j * d + t] : 0.0;
+    cb16[(int64_t)j * kd16 + t] = f32_to_bf16((float)(-2.0 * c));
+    acc += c * c;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) cnB[j] = (float)(acc + (double)st->B);
+}
+
+hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, const PassState* st,
+                     uint16_t* cb16, float* cnB, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_bf16, dim3(k), dim3(64), 0, s, c64, k, d, kd16, st, cb16, cnB);
+  return hipGetLastError();
 }
 
 // ============================================================================
@@ -1342,45 +1825,69 @@ static void visit_tiled(int dmax, F&& f) {
 
 // Resident blocks of 256 threads per CU for a kernel with `lds` bytes of dynamic LDS.
 template <typename K>
-static int64_t resident_blocks(K kernel, size_t lds, int cus) {
+static int64_t resident_blocks(K kernel, size_t lds, int cus, int threads = 256) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, lds) != hipSuccess || nb < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, lds) != hipSuccess ||
+      nb < 1)
     nb = 1;
   return (int64_t)nb * std::max(1, cus);
+}
+
+template <typename T, int MODE, typename F>
+static void visit_bf16(int ks, F&& f) {
+  switch (ks) {
+    case 1: f(k_assign_bf16<T, 1, 2, MODE>); break;
+    case 2: f(k_assign_bf16<T, 2, 2, MODE>); break;
+    case 4: f(k_assign_bf16<T, 4, 2, MODE>); break;
+    case 8: f(k_assign_bf16<T, 8, 2, MODE>); break;
+    default: f(k_assign_bf16<T, 16, 1, MODE>); break;
+  }
 }
 
 template <typename T>
 static int64_t plan_blocks(const PassPlan& p, int cus) {
   int64_t r = 0;
   auto f = [&](auto kern) { r = resident_blocks(kern, p.lds_assign, cus); };
-  if (p.mfma) visit_mfma<T>(p.kd, p.nt, f);
+  if (p.bf16) visit_bf16<T, 0>(p.ks, [&](auto kern) { r = resident_blocks(kern, 0, cus, 512); });
+  else if (p.mfma) visit_mfma<T>(p.kd, p.nt, f);
   else if (p.fused) visit_fused<T>(p.dmax, f);
   else if (p.dmax) visit_tiled<T>(p.dmax, f);
   else r = resident_blocks(k_assign_generic<T>, 0, cus);
   return r;
 }
 
-PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, size_t lds_limit, int cus) {
+PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
+                   size_t lds_limit, int cus) {
   PassPlan p{};
   p.dmax = pick_dmax(d);
   p.ppt = pick_ppt(p.dmax);
   const size_t budget = std::min<size_t>(lds_limit, 65536);
   const size_t kk = (size_t)k, dd = (size_t)d;
+  // BF16 screen: asked for, or automatic for BF16 data with d >= 32 (precision
+  // codes follow km_precision: 0 auto, 1 FP32, 2 BF16 screen)
+  p.bf16 = d <= 256 && (precision == 2 || (precision == 0 && dtype == 1 && d >= 32));
+  if (p.bf16) {
+    p.ks = d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 4 : d <= 128 ? 8 : 16;
+    p.dmax = 0;
+  }
   // MFMA fused pass: d <= 32, k <= 128, LDS for FP64 centers + sums + counts
   const size_t lds_mfma = kk * (dd + 1) * 8 * 2;
   const size_t lds_fused = ((kk * (size_t)p.dmax + kk) * 4 + 15) / 16 * 16 + kk * (dd + 1) * 8;
   int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
-  if (d <= 32 && k <= 128 && lds_mfma <= budget) {
+  if (p.bf16) {
+    work = (rows + 511) / 512;
+  } else if (d <= 32 && k <= 128 && lds_mfma <= budget) {
     p.mfma = true;
     p.fused = true;
     p.kd = p.dmax;
     p.nt = (k + 31) / 32;
     p.lds_assign = lds_mfma;
     work = ((rows + 31) / 32 + 3) / 4;
-  } else {
-    p.fused = p.dmax != 0 && lds_fused <= budget;
+  }
+  if (!p.mfma) {
+    p.fused = !p.bf16 && p.dmax != 0 && lds_fused <= budget;
     const int64_t tile_pts = 256LL * p.ppt;
-    work = (rows + tile_pts - 1) / tile_pts;
+    if (!p.bf16) work = (rows + tile_pts - 1) / tile_pts;
     if (p.fused) {
       p.lds_assign = lds_fused;
       p.ktile = k;
@@ -1389,18 +1896,19 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, size_t lds_lim
         p.ktile = (int)std::max<int64_t>(1, std::min<int64_t>(k, 8192 / p.dmax));
         p.lds_assign = (size_t)p.ktile * p.dmax * 4 + (size_t)p.ktile * 4;
       }
-      // split update: crange centers x slice dims of 64-bit sums + crange counts in LDS
+      // split update: crange centers x slice dims of 64-bit sums, plus crange
+      // squared-norm sums and counts, in LDS
       int crange = k, slice;
-      if (kk * 12 > budget) {
-        crange = (int)(budget / 12);
+      if (kk * 20 > budget) {
+        crange = (int)(budget / 20);
         slice = 1;
       } else {
-        slice = (int)std::min<size_t>(dd, (budget - kk * 4) / (kk * 8));
+        slice = (int)std::min<size_t>(dd, (budget - kk * 12) / (kk * 8));
       }
       p.crange = crange;
       p.slice = std::max(1, slice);
       p.nslices = (d + p.slice - 1) / p.slice;
-      p.lds_update = (size_t)crange * p.slice * 8 + (size_t)crange * 4;
+      p.lds_update = (size_t)crange * p.slice * 8 + (size_t)crange * 12;
       p.ublocks = std::max<int64_t>(1, std::min<int64_t>((rows + 2047) / 2048, 1024));
     }
   }
@@ -1439,23 +1947,45 @@ static void dispatch_tiled(const PassBufs& b, const PassPlan& p, const int32_t* 
 }
 
 static void split_update(const PassBufs& b, const PassPlan& p, const int32_t* gate,
-                         hipStream_t s) {
+                         long long* qslots, hipStream_t s) {
   const int crange = p.crange;
   const unsigned ncr = (unsigned)((b.k + crange - 1) / crange);
   dim3 grid((unsigned)p.ublocks, (unsigned)p.nslices, ncr);
   if (b.dtype == 0)
     hipLaunchKernelGGL(k_update_split<float>, grid, dim3(256), p.lds_update, s,
                        (const float*)b.X, (const int32_t*)b.labels, b.n, b.d, b.k, p.slice,
-                       crange, (const PassState*)b.st, gate, b.slots);
+                       crange, (const PassState*)b.st, gate, b.slots, qslots);
   else
     hipLaunchKernelGGL(k_update_split<uint16_t>, grid, dim3(256), p.lds_update, s,
                        (const uint16_t*)b.X, (const int32_t*)b.labels, b.n, b.d, b.k, p.slice,
-                       crange, (const PassState*)b.st, gate, b.slots);
+                       crange, (const PassState*)b.st, gate, b.slots, qslots);
+}
+
+template <typename T>
+static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* gate,
+                          hipStream_t s) {
+  visit_bf16<T, 0>(p.ks, [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(512), 0, s, (const T*)b.X, b.n, b.d,
+                       b.k, (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
+                       (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr, b.Jpart,
+                       b.upart);
+  });
+  // the points with more than four candidates, re-screened (the second half of the
+  // per-block counters is theirs)
+  visit_bf16<T, 1>(p.ks, [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(512), 0, s, (const T*)b.X, b.n, b.d,
+                       b.k, (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
+                       (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr,
+                       b.Jpart + p.blocks, b.upart + 2 * p.blocks);
+  });
 }
 
 hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
   const int32_t* gate = update ? &b.st->done : nullptr;
-  if (p.fused) {
+  if (p.bf16) {
+    if (b.dtype == 0) dispatch_bf16<float>(b, p, gate, s);
+    else dispatch_bf16<uint16_t>(b, p, gate, s);
+  } else if (p.fused) {
     if (b.dtype == 0) dispatch_fused<float>(b, p, update, gate, s);
     else dispatch_fused<uint16_t>(b, p, update, gate, s);
   } else {
@@ -1467,15 +1997,20 @@ hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStr
 
 hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
   const int32_t* gate = update ? &b.st->done : nullptr;
-  if (update) {
-    if (!p.fused) split_update(b, p, gate, s);
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(256), 0, s, b.slots, b.k, b.d, b.st,
-                       gate, b.c64, b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out,
-                       (const double*)b.Jpart, (const long long*)b.upart, p.blocks, b.J_hist,
+  const int64_t nb = p.bf16 ? 2 * p.blocks : p.blocks;
+  // the BF16 screen leaves J to the cluster sums, so it needs them in a labelling
+  // pass too; the FP32 kernels add J per point
+  long long* qslots = p.bf16 ? b.qslots : nullptr;
+  if (update || p.bf16) {
+    if (!p.fused) split_update(b, p, gate, qslots, s);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(256), 0, s, b.slots, qslots, b.k, b.d, b.st, gate, update ? 1 : 0, b.c64,
+                       b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out, b.Jc,
+                       p.bf16 ? b.cb16 : nullptr, p.bf16 ? b.cnB : nullptr, p.ks * 16,
+                       (const double*)b.Jpart, (const long long*)b.upart, nb, b.J_hist,
                        b.shift_hist);
   } else {
     hipLaunchKernelGGL(k_sum_J, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
-                       (const long long*)b.upart, p.blocks);
+                       (const long long*)b.upart, nb);
   }
   return hipGetLastError();
 }

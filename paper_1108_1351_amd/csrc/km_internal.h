@@ -32,7 +32,11 @@ struct PassState {
   float scale;         // 2^F
   float cmax;          // upper bound of max_j ||c_j||, for the FP32 error bound
   uint32_t maxabs_bits;  // bits of max |x| over the stage's rows (NaN/Inf -> >= 0x7f800000)
+  uint32_t xn2max_bits;  // bits of max ||x||^2 over the stage's rows
   uint32_t ticket;     // blocks of the finalize kernel that are done (last one concludes)
+  uint32_t qcount;     // points queued for the BF16 re-screen in this pass
+  int32_t FQ;          // squared norms add rint(||x_slice||^2 * 2^FQ) as 64-bit integers
+  float B;             // score offset >= max ||x||^2 of the BF16 screen (keeps scores >= 0)
   int32_t nonfinite;
   int32_t empty;
   int32_t converged;
@@ -58,16 +62,26 @@ hipError_t stage_reset(PassState* st, hipStream_t s);
 hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
                      hipStream_t s);
 hipError_t zero_i64(long long* p, int64_t count, hipStream_t s);
+hipError_t row_norms(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
+                     hipStream_t s);
+hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, const PassState* st,
+                     uint16_t* cb16, float* cnB, hipStream_t s);
 hipError_t prep_centers(const double* c64, int32_t k, int32_t d, float* cw, float* cn,
                         double* cnorm, hipStream_t s);
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
-                       const double* cnorm, int32_t k, hipStream_t s);
+                       const double* cnorm, int32_t k, int32_t d, hipStream_t s);
 
 struct PassBufs {
   const void* X; int dtype; int64_t n; int32_t d; int32_t k;
   double* c64; float* cw; float* cn; double* cnorm;
   double* shiftj; int32_t* emptyj;
   long long* slots;    // [kSlots][k][d+1] exact cluster sums (counts last); zero between passes
+  long long* qslots;   // [kSlots][k] exact sums of squared norms (split path); zero between passes
+  double* Jc;          // [k] per-cluster J of the split path
+  uint16_t* cb16;      // [k][ks*16] BF16 centers of the BF16 screen
+  float* cnB;          // [k] ||c||^2 + B of the BF16 screen
+  int32_t* queue;      // [n] points of the BF16 screen with more than 4 candidates
+  float* qthr;         // [n] their score thresholds
   double* Jpart; long long* upart;
   int32_t* labels;     // labels of the rows (required by the split path)
   PassState* st;
@@ -77,6 +91,8 @@ struct PassBufs {
 
 // Geometry chosen once per (rows, d, k): fused or split path and block counts.
 struct PassPlan {
+  bool bf16;         // split pass with the BF16 MFMA screen (x.c^T as 32x32x16 tiles)
+  int ks;            // 16-dim K steps of the BF16 screen
   bool mfma;         // fused pass on FP32 MFMA (x.c^T as 32x32x2 tiles)
   int kd, nt;        // padded dims and 32-center tiles of the MFMA kernel
   bool fused;
@@ -91,7 +107,8 @@ struct PassPlan {
   int ktile;         // centers per LDS tile (split assign)
 };
 
-PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, size_t lds_limit, int cus);
+PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
+                   size_t lds_limit, int cus);
 hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
 // the assignment kernel of a pass, and everything after it (update, reduction, stop test)
 hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
