@@ -2,17 +2,21 @@
 """Benchmark of the two-stage k-means hot path on one MI355X.
 
 A step is one complete two-stage fit -- fast-stage sampling, the fast stage on
-the subset, the slow stage on all points, the final labelling pass -- of the
-10,000,000 x 16-D, k = 64 Gaussian-mixture workload (FP32), with X resident in
-HBM before the timed region.  ``value`` is distance evaluations per second of
-the whole job: k*(m*Q_f + n*Q_s) + k*n evaluations per fit (section 3 of the
-paper counts the method's cost in these units) over the fit's wall time.
+the subset, the slow stage on all points, the final labelling pass -- of a
+Gaussian-mixture workload (default: 10,000,000 x 16-D FP32, k = 64), with X
+resident in HBM before the timed region.  ``value`` is distance evaluations
+per second of the whole job: k*(m*Q_f + n*Q_s) + k*n evaluations per fit
+(section 3 of the paper counts the method's cost in these units) over the
+fit's wall time.
 
 The roofline object covers the dominant kernel, the slow stage's assignment
-kernel: its duration is measured live with HIP events on the stream it runs
-on (the library's pass profiler), and its algorithmic work per launch is
-2*n*k*d FP32 flops and n*d*4 bytes.  The CPU baseline is the FP64 oracle
-timed on a bounded sample of the same workload on the host's cores.
+kernel (for BF16 data, its BF16 MFMA screen): its duration is measured live
+with HIP events on the stream it runs on (the library's pass profiler).  Its
+algorithmic work per launch is 2*n*k*d flops and n*d*s bytes (s = bytes per
+element); the bound is whichever of HBM bandwidth and the arithmetic peak
+(FP32 vector for the FP32 kernels, dense BF16 MFMA for the screen) allows
+less.  The CPU baseline is the FP64 oracle timed on a bounded sample of the
+same workload on the host's cores.
 """
 from __future__ import annotations
 
@@ -28,7 +32,11 @@ sys.path.insert(0, ROOT)
 
 WORKLOAD = "gmm16d_n1e7_k64"
 PEAK_FP32_TFLOPS = 157.3        # MI355X published FP32 vector/matrix peak
+PEAK_BF16_TFLOPS = 2500.0       # MI355X published dense BF16 MFMA peak
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
+# rows of the CPU-baseline sample per workload (about 10-30 s of oracle work)
+CPU_ROWS = {"gmm2d_n1e5_k8": 100_000, "gmm16d_n1e7_k64": 2_000_000,
+            "gmm128d_n1e8_k1024_bf16": 40_000, "gmm4d_n5e8_k32": 20_000_000}
 METRIC = "distance evals/s & % roofline per Lloyd iter; batched p50/p99 solve latency"
 
 
@@ -79,7 +87,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=WORKLOAD)
-    ap.add_argument("--cpu-rows", type=int, default=2_000_000)
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="rows of the CPU-baseline sample (default: per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (HBM counter scale)")
@@ -110,7 +119,13 @@ def main() -> int:
     host = torch.empty((w.n, w.d), dtype=torch.float32 if w.dtype == "f32" else torch.int16,
                        pin_memory=True)
     hv = host.numpy() if w.dtype == "f32" else host.numpy().view(np.uint16)
-    w.data(out=hv)
+    chunk = 10_000_000
+    prm = synth.params(w.spec, w.data_seed)
+    for r0 in range(0, w.n, chunk):
+        r1 = min(w.n, r0 + chunk)
+        synth.generate(w.spec, w.data_seed, r1 - r0, w.dtype, row0=r0, out=hv[r0:r1], prm=prm)
+        if w.n > chunk:
+            print(f"[bench] generated rows {r0:,}..{r1:,}", file=sys.stderr, flush=True)
     X = host.to("cuda", non_blocking=False)
     if w.dtype == "bf16":
         X = X.view(torch.bfloat16)
@@ -147,15 +162,24 @@ def main() -> int:
     rows = prof["rows"][1] / max(1, launches)
     flops = 2.0 * rows * w.k * w.d
     algo_bytes = rows * w.d * (4 if w.dtype == "f32" else 2)
-    achieved = flops / avg_s / 1e12
+    bf16_screen = w.dtype == "bf16" and w.d >= 32
+    peak_flops = PEAK_BF16_TFLOPS if bf16_screen else PEAK_FP32_TFLOPS
     traffic = read_traffic(w.name)
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": traffic,
-                "kernel": "slow-stage assignment kernel (fused assign + cluster sums)",
-                "launches": launches, "avg_launch_us": avg_s * 1e6,
-                "flops_per_launch": flops, "algo_bytes_per_launch": algo_bytes,
-                "algo_hbm_GBs": algo_bytes / avg_s / 1e9}
+    if algo_bytes / (PEAK_HBM_GBS * 1e9) > flops / (peak_flops * 1e12):
+        achieved = algo_bytes / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        achieved = flops / avg_s / 1e12
+        roofline = {"bound": "mfma" if bf16_screen else "alu", "achieved": achieved,
+                    "peak": peak_flops, "unit": "TFLOP/s"}
+    roofline.update({
+        "frac": roofline["achieved"] / roofline["peak"], "traffic": traffic,
+        "kernel": ("slow-stage BF16 MFMA screen (top-4 keys, FP32 re-rank, FP64 decisions)"
+                   if bf16_screen else
+                   "slow-stage assignment kernel (fused assign + cluster sums)"),
+        "launches": launches, "avg_launch_us": avg_s * 1e6,
+        "flops_per_launch": flops, "algo_bytes_per_launch": algo_bytes,
+        "achieved_TFLOPs": flops / avg_s / 1e12, "algo_hbm_GBs": algo_bytes / avg_s / 1e9})
     pass_s = prof["pass_ms"][1] / 1e3 / max(1, launches)
     out = {
         "metric": METRIC,
@@ -182,8 +206,9 @@ def main() -> int:
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        print(f"[bench] cpu baseline on {args.cpu_rows} rows", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows)
+        cpu_rows = min(w.n, args.cpu_rows or CPU_ROWS.get(w.name, 1_000_000))
+        print(f"[bench] cpu baseline on {cpu_rows} rows", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, cpu_rows)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -1970,8 +1970,13 @@ static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* g
                        (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr, b.Jpart,
                        b.upart);
   });
-  // the points with more than four candidates, re-screened (the second half of the
-  // per-block counters is theirs)
+}
+
+// The points with more than four candidates, re-screened (the second half of
+// the per-block counters is theirs).
+template <typename T>
+static void dispatch_rescreen(const PassBufs& b, const PassPlan& p, const int32_t* gate,
+                              hipStream_t s) {
   visit_bf16<T, 1>(p.ks, [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(512), 0, s, (const T*)b.X, b.n, b.d,
                        b.k, (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
@@ -2001,6 +2006,10 @@ hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStrea
   // the BF16 screen leaves J to the cluster sums, so it needs them in a labelling
   // pass too; the FP32 kernels add J per point
   long long* qslots = p.bf16 ? b.qslots : nullptr;
+  if (p.bf16) {
+    if (b.dtype == 0) dispatch_rescreen<float>(b, p, gate, s);
+    else dispatch_rescreen<uint16_t>(b, p, gate, s);
+  }
   if (update || p.bf16) {
     if (!p.fused) split_update(b, p, gate, qslots, s);
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(256), 0, s, b.slots, qslots, b.k, b.d, b.st, gate, update ? 1 : 0, b.c64,

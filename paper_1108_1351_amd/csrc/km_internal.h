@@ -110,7 +110,8 @@ struct PassPlan {
 PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
                    size_t lds_limit, int cus);
 hipError_t lloyd_pass(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
-// the assignment kernel of a pass, and everything after it (update, reduction, stop test)
+// the assignment kernel of a pass (for the BF16 path, its screen of all points), and
+// everything after it (re-screen, update, reduction, stop test)
 hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
 hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s);
 hipError_t assign_only(const PassBufs& b, const PassPlan& p, hipStream_t s);
