@@ -105,7 +105,8 @@ struct Carver {
 
 struct Layout {
   size_t sel, hist, blk, sub, init_sel, init_key, xs, c64, cw, cn, cnorm, shiftj, emptyj, st,
-      jh, sh, slots, qslots, jc, cb16, cnb, queue, qthr, jpart, upart, labels;
+      jh, sh, slots, jslots, cb16, cnb, queue, qthr, jpart, upart, labels, perm, scnt, stot,
+      rstart;
   size_t bytes;
   bool labels_ws;
 };
@@ -129,6 +130,26 @@ int64_t blocks_max(const Sizes& z) {
 bool any_bf16(const Sizes& z) { return (z.stage1 && z.p1.bf16) || z.p2.bf16; }
 int ks_max(const Sizes& z) { return std::max(z.stage1 ? z.p1.ks : 0, z.p2.ks); }
 
+// Buffers of the sorted update (split paths), sized for the larger stage.
+struct SortSizes {
+  size_t perm, cnt, tiles, starts;
+};
+
+SortSizes sort_sizes(const PassPlan* p1, const PassPlan* p2, int64_t m, int64_t n, int32_t k) {
+  SortSizes o{0, 0, 0, 0};
+  auto add = [&](const PassPlan* p, int64_t rows) {
+    if (!p || p->fused) return;
+    const size_t cn = (size_t)k * (size_t)p->sort_chunks;
+    o.perm = std::max(o.perm, (size_t)rows);
+    o.cnt = std::max(o.cnt, cn);
+    o.tiles = std::max(o.tiles, (cn + 2047) / 2048 + 1);
+    o.starts = std::max(o.starts, (size_t)k + 1);
+  };
+  add(p1, m);
+  add(p2, n);
+  return o;
+}
+
 Layout make_layout(const Sizes& z) {
   Layout L{};
   Carver c;
@@ -151,8 +172,7 @@ Layout make_layout(const Sizes& z) {
   L.sh = c.take<double>((size_t)z.hist_len);
   const size_t C = (size_t)z.k * (z.d + 1);
   L.slots = c.take<long long>((size_t)kSlots * C);
-  L.qslots = c.take<long long>((size_t)kSlots * z.k);
-  L.jc = c.take<double>((size_t)z.k);
+  L.jslots = c.take<long long>((size_t)kSlots * 2);
   L.cb16 = c.take<uint16_t>(any_bf16(z) ? (size_t)z.k * 16 * ks_max(z) : 0);
   L.cnb = c.take<float>((size_t)z.k);
   L.queue = c.take<int32_t>(any_bf16(z) ? (size_t)z.n : 0);
@@ -161,6 +181,11 @@ Layout make_layout(const Sizes& z) {
   L.upart = c.take<long long>((size_t)blocks_max(z) * 2);
   L.labels_ws = z.need_labels_ws;
   L.labels = c.take<int32_t>(z.need_labels_ws ? (size_t)z.n : 0);
+  const SortSizes so = sort_sizes(z.stage1 ? &z.p1 : nullptr, &z.p2, z.m, z.n, z.k);
+  L.perm = c.take<uint32_t>(so.perm);
+  L.scnt = c.take<long long>(so.cnt);
+  L.stot = c.take<long long>(so.tiles);
+  L.rstart = c.take<long long>(so.starts);
   L.bytes = c.off;
   return L;
 }
@@ -287,12 +312,11 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
   if (prof)
     for (int32_t i = 0; i < 3 * max_iter; ++i) ev.push_back(take_event());
   HIP_TRY(stage_reset(b.st, s));
-  HIP_TRY(row_stats(b.X, b.dtype, rows, b.d, b.st, s));
-  if (plan.bf16) HIP_TRY(row_norms(b.X, b.dtype, rows, b.d, b.st, s));
-  HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, b.d, s));
+  HIP_TRY(row_stats(b.X, b.dtype, rows, b.d, !plan.fused, b.st, s));
+  HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, b.d, plan.fused ? 0 : plan.pg, s));
   if (plan.bf16) HIP_TRY(prep_bf16(b.c64, b.k, b.d, plan.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * b.k * (b.d + 1), s));
-  HIP_TRY(zero_i64(b.qslots, (int64_t)kSlots * b.k, s));
+  HIP_TRY(zero_i64(b.jslots, (int64_t)kSlots * 2, s));
   while (launched < max_iter) {
     const int32_t q = std::min(chunk, max_iter - launched);
     for (int32_t i = 0; i < q; ++i) {
@@ -408,6 +432,9 @@ static bool fit_sizes(int64_t n, int32_t d, int32_t k, double f, const km_option
   z->p1 = plan_pass(z->m, d, k, dt, (int)opt->precision, lds, device_cus());
   z->p2 = plan_pass(n, d, k, dt, (int)opt->precision, lds, device_cus());
   z->need_labels_ws = !labels_given && ((z->stage1 && !z->p1.fused) || !z->p2.fused);
+  if (!z->p2.fused && n > (int64_t)UINT32_MAX)
+    return !fail(KM_EINVAL, "n = %lld rows need the sorted update, which takes n < 2^32",
+                 (long long)n);
   return true;
 }
 
@@ -466,14 +493,17 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
   b.shiftj = at<double>(base, L.shiftj);
   b.emptyj = at<int32_t>(base, L.emptyj);
   b.slots = at<long long>(base, L.slots);
-  b.qslots = at<long long>(base, L.qslots);
-  b.Jc = at<double>(base, L.jc);
+  b.jslots = at<long long>(base, L.jslots);
   b.cb16 = at<uint16_t>(base, L.cb16);
   b.cnB = at<float>(base, L.cnb);
   b.queue = at<int32_t>(base, L.queue);
   b.qthr = at<float>(base, L.qthr);
   b.Jpart = at<double>(base, L.jpart);
   b.upart = at<long long>(base, L.upart);
+  b.perm = at<uint32_t>(base, L.perm);
+  b.scnt = at<long long>(base, L.scnt);
+  b.stot = at<long long>(base, L.stot);
+  b.rstart = at<long long>(base, L.rstart);
   b.st = st;
   HIP_TRY(hipMemsetAsync(hist, 0, sizeof(unsigned long long) * kSelBins, s));
 
@@ -630,19 +660,25 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   const PassPlan p = plan_pass(n, d, k, dtype == KM_F32 ? 0 : 1, (int)precision,
                                device_lds_limit(), device_cus());
   const bool lab_ws = !labels && !p.fused;
+  if (!p.fused && n > (int64_t)UINT32_MAX)
+    return fail(KM_EINVAL, "n = %lld rows need the sorted update, which takes n < 2^32",
+                (long long)n);
   Carver c;
   const size_t C_ = (size_t)k * (d + 1);
   const size_t o_c64 = c.take<double>((size_t)k * d), o_cw = c.take<float>((size_t)k * d),
                o_cn = c.take<float>(k), o_cnorm = c.take<double>(k),
                o_sh = c.take<double>(k), o_em = c.take<int32_t>(k),
                o_st = c.take<PassState>(1), o_slots = c.take<long long>((size_t)kSlots * C_),
-               o_qs = c.take<long long>((size_t)kSlots * k), o_jc = c.take<double>(k),
+               o_qs = c.take<long long>((size_t)kSlots * 2),
                o_cb = c.take<uint16_t>(p.bf16 ? (size_t)k * 16 * p.ks : 0),
                o_cnb = c.take<float>(k), o_q = c.take<int32_t>(p.bf16 ? (size_t)n : 0),
                o_qt = c.take<float>(p.bf16 ? (size_t)n : 0),
                o_jp = c.take<double>((size_t)p.blocks * 2),
                o_up = c.take<long long>((size_t)p.blocks * 4),
                o_lab = c.take<int32_t>(lab_ws ? (size_t)n : 0);
+  const SortSizes so = sort_sizes(nullptr, &p, 0, n, k);
+  const size_t o_perm = c.take<uint32_t>(so.perm), o_scnt = c.take<long long>(so.cnt),
+               o_stot = c.take<long long>(so.tiles), o_rst = c.take<long long>(so.starts);
   DevMem mem;
   km_status rc = mem.get(c.off, nullptr, 0, s);
   if (rc != KM_OK) return rc;
@@ -661,8 +697,7 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   b.shiftj = at<double>(base, o_sh);
   b.emptyj = at<int32_t>(base, o_em);
   b.slots = at<long long>(base, o_slots);
-  b.qslots = at<long long>(base, o_qs);
-  b.Jc = at<double>(base, o_jc);
+  b.jslots = at<long long>(base, o_qs);
   b.cb16 = at<uint16_t>(base, o_cb);
   b.cnB = at<float>(base, o_cnb);
   b.queue = at<int32_t>(base, o_q);
@@ -670,18 +705,21 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   b.Jpart = at<double>(base, o_jp);
   b.upart = at<long long>(base, o_up);
   b.labels = labels ? labels : (lab_ws ? at<int32_t>(base, o_lab) : nullptr);
+  b.perm = at<uint32_t>(base, o_perm);
+  b.scnt = at<long long>(base, o_scnt);
+  b.stot = at<long long>(base, o_stot);
+  b.rstart = at<long long>(base, o_rst);
   b.st = at<PassState>(base, o_st);
   b.S_out = S;
   b.N_out = N;
   HIP_TRY(hipMemcpyAsync(b.c64, C, sizeof(double) * k * d, hipMemcpyDeviceToDevice, s));
   HIP_TRY(prep_centers(b.c64, k, d, b.cw, b.cn, b.cnorm, s));
   HIP_TRY(stage_reset(b.st, s));
-  HIP_TRY(row_stats(X, b.dtype, n, d, b.st, s));
-  if (p.bf16) HIP_TRY(row_norms(X, b.dtype, n, d, b.st, s));
-  HIP_TRY(stage_begin(b.st, 1, 0.0, n, b.cnorm, k, d, s));
+  HIP_TRY(row_stats(X, b.dtype, n, d, !p.fused, b.st, s));
+  HIP_TRY(stage_begin(b.st, 1, 0.0, n, b.cnorm, k, d, p.fused ? 0 : p.pg, s));
   if (p.bf16) HIP_TRY(prep_bf16(b.c64, k, d, p.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * k * (d + 1), s));
-  HIP_TRY(zero_i64(b.qslots, (int64_t)kSlots * k, s));
+  HIP_TRY(zero_i64(b.jslots, (int64_t)kSlots * 2, s));
   HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (hs.nonfinite) return fail(KM_EINVAL, "X contains NaN or Inf");

@@ -337,84 +337,115 @@ hipError_t stage_reset(PassState* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Per stage: max |x| over the rows (NaN/Inf show as bits >= 0x7f800000).
-template <typename T>
-__global__ __launch_bounds__(256) void k_row_stats(const T* __restrict__ X, int64_t count,
-                                                   PassState* __restrict__ st) {
-  uint32_t mx = 0u;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride)
-    mx = max(mx, __float_as_uint(widen<T>(X[e])) & 0x7fffffffu);
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o));
-  __shared__ uint32_t w[4];
-  if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicMax(&st->maxabs_bits, max(max(w[0], w[1]), max(w[2], w[3])));
-}
-
-hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
-                     hipStream_t s) {
-  const int64_t count = rows * d;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 4096));
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_row_stats<float>, dim3(g), dim3(256), 0, s, (const float*)X, count, st);
-  else
-    hipLaunchKernelGGL(k_row_stats<uint16_t>, dim3(g), dim3(256), 0, s, (const uint16_t*)X, count,
-                       st);
-  return hipGetLastError();
-}
-
-// Max ||x||^2 over the rows (thread per row; rows of 16 bytes loaded at once
-// when aligned).  Needed by the BF16 screen only.
-template <typename T>
-__global__ __launch_bounds__(256) void k_row_norms(const T* __restrict__ X, int64_t rows, int d,
-                                                   PassState* __restrict__ st) {
-  float xn2 = 0.f;
-  constexpr int V = 16 / sizeof(T);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows; i += stride) {
-    const T* xr = X + i * d;
-    float s2 = 0.f;
-    int t = 0;
-    if ((reinterpret_cast<uintptr_t>(xr) & 15u) == 0) {
-      for (; t + V <= d; t += V) {
-        const uint4 v = *reinterpret_cast<const uint4*>(xr + t);
-        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+// E consecutive elements of a row widened to FP32: one 16-byte load when E
+// elements fill 16 bytes (the caller guarantees the alignment), else E loads.
+template <typename T, int E>
+__device__ __forceinline__ void load_vec(const T* __restrict__ p, bool ok, float (&v)[E]) {
+  if constexpr (E * sizeof(T) == 16) {
+    uint4 w = make_uint4(0u, 0u, 0u, 0u);
+    if (ok) w = *reinterpret_cast<const uint4*>(p);
+    const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if constexpr (sizeof(T) == 4) {
-            const float f = __uint_as_float(w4[u]);
-            s2 = __builtin_fmaf(f, f, s2);
-          } else {
-            const float f0 = __uint_as_float(w4[u] << 16), f1 = __uint_as_float(w4[u] & 0xffff0000u);
-            s2 = __builtin_fmaf(f0, f0, s2);
-            s2 = __builtin_fmaf(f1, f1, s2);
-          }
-        }
+    for (int u = 0; u < 4; ++u) {
+      if constexpr (sizeof(T) == 4) {
+        v[u] = __uint_as_float(w4[u]);
+      } else {
+        v[2 * u] = __uint_as_float(w4[u] << 16);
+        v[2 * u + 1] = __uint_as_float(w4[u] & 0xffff0000u);
       }
     }
-    for (; t < d; ++t) {
-      const float f = widen<T>(xr[t]);
-      s2 = __builtin_fmaf(f, f, s2);
-    }
-    xn2 = fmaxf(xn2, s2);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = ok ? widen<T>(p[e]) : 0.f;
   }
-  for (int o = 32; o > 0; o >>= 1) xn2 = fmaxf(xn2, __shfl_xor(xn2, o));
-  __shared__ float wn[4];
-  if ((threadIdx.x & 63) == 0) wn[threadIdx.x >> 6] = xn2;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    atomicMax(&st->xn2max_bits, __float_as_uint(fmaxf(fmaxf(wn[0], wn[1]), fmaxf(wn[2], wn[3]))));
 }
 
-hipError_t row_norms(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
-                     hipStream_t s) {
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((rows + 255) / 256, 8192));
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_row_norms<float>, dim3(g), dim3(256), 0, s, (const float*)X, rows, d, st);
-  else
-    hipLaunchKernelGGL(k_row_norms<uint16_t>, dim3(g), dim3(256), 0, s, (const uint16_t*)X, rows,
-                       d, st);
+// Elements per lane of the row-group kernels: 16 bytes when every row starts
+// on a 16-byte boundary, else one.
+int row_vec(int dtype, int32_t d, const void* X) {
+  const int E = dtype == 0 ? 4 : 8;
+  const size_t s = dtype == 0 ? 4 : 2;
+  const bool aligned = ((size_t)d * s) % 16 == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  return aligned ? E : 1;
+}
+
+// log2 of the lanes that cover one row: E*G >= d, G a power of two <= 64.
+int row_glog(int32_t d, int E) {
+  const int64_t need = ((int64_t)d + E - 1) / E;
+  int g = 0;
+  while ((1 << g) < need && g < 6) ++g;
+  return g;
+}
+
+// Per stage: max |x| over all elements (NaN/Inf show as bits >= 0x7f800000) and,
+// with norms, max ||x||^2 over the rows.  A group of G = 2^glog lanes covers a
+// row, each lane E consecutive elements per column step, so a wave reads whole
+// rows with 16-byte loads.
+template <typename T, int E>
+__global__ __launch_bounds__(256) void k_row_stats(const T* __restrict__ X, int64_t rows, int d,
+                                                   int glog, int norms,
+                                                   PassState* __restrict__ st) {
+  const int G = 1 << glog;
+  const int lane = threadIdx.x & 63, gi = lane >> glog, gl = lane & (G - 1);
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t step = (int64_t)gridDim.x * 4 * (64 >> glog);
+  uint32_t mx = 0u;
+  float xn2 = 0.f;
+  for (int64_t base = wave * (64 >> glog); base < rows; base += step) {
+    const int64_t r = base + gi;
+    const bool valid = r < rows;
+    const T* xr = X + (valid ? r : 0) * d;
+    float s2 = 0.f;
+    for (int c0 = gl * E; c0 < d; c0 += G * E) {
+      float v[E];
+      load_vec<T, E>(xr + c0, valid, v);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool in = E == 1 || c0 + e < d;
+        const float f = in ? v[e] : 0.f;
+        mx = max(mx, __float_as_uint(f) & 0x7fffffffu);
+        s2 = __builtin_fmaf(f, f, s2);
+      }
+    }
+    if (norms) {
+      for (int o = G >> 1; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
+      xn2 = fmaxf(xn2, s2);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o));
+    xn2 = fmaxf(xn2, __shfl_xor(xn2, o));
+  }
+  __shared__ uint32_t w[4];
+  __shared__ float wn[4];
+  if (lane == 0) {
+    w[threadIdx.x >> 6] = mx;
+    wn[threadIdx.x >> 6] = xn2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(&st->maxabs_bits, max(max(w[0], w[1]), max(w[2], w[3])));
+    if (norms)
+      atomicMax(&st->xn2max_bits,
+                __float_as_uint(fmaxf(fmaxf(wn[0], wn[1]), fmaxf(wn[2], wn[3]))));
+  }
+}
+
+hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, bool norms,
+                     PassState* st, hipStream_t s) {
+  const int E = row_vec(dtype, d, X), glog = row_glog(d, E);
+  const int64_t waves = (rows + (64 >> glog) - 1) / (64 >> glog);
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((waves + 3) / 4, 8192));
+  auto go = [&](auto kern, auto* x) {
+    hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, x, rows, d, glog, norms ? 1 : 0, st);
+  };
+  if (dtype == 0) {
+    if (E == 4) go(k_row_stats<float, 4>, (const float*)X);
+    else go(k_row_stats<float, 1>, (const float*)X);
+  } else {
+    if (E == 8) go(k_row_stats<uint16_t, 8>, (const uint16_t*)X);
+    else go(k_row_stats<uint16_t, 1>, (const uint16_t*)X);
+  }
   return hipGetLastError();
 }
 
@@ -465,7 +496,7 @@ __device__ __forceinline__ int ceil_log2(int64_t v) {
 __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
                                                      int32_t max_iter, double tol, int64_t rows,
                                                      const double* __restrict__ cnorm,
-                                                     int32_t k, int32_t d_) {
+                                                     int32_t k, int32_t d_, int64_t pg) {
   __shared__ double red[256];
   double m = 0.0;
   for (int j = threadIdx.x; j < k; j += 256) m = fmax(m, cnorm[j]);
@@ -487,21 +518,25 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
     }
     st->F = F;
     st->scale = ldexpf(1.0f, F);
-    // the FP32 sum of squares of a row is within d * 2^-24 <= 2^-16 (d <= 256) of
-    // ||x||^2, so xm bounds every row's squared norm
-    const float xm = __uint_as_float(st->xn2max_bits) * (1.0f + 0x1p-10f);
-    // squared norms of row slices add as rint(q * 2^FQ): a row's parts sum to at
-    // most 2^(61 - ceil_log2(rows)) (plus a half per slice), so rows of them stay
-    // below 2^62
-    int FQ = 0;
-    if (st->xn2max_bits != 0u && !st->nonfinite) {
-      FQ = 60 - ilogbf(xm) - ceil_log2(rows);
-      FQ = min(200, max(-200, FQ));
+    // the FP32 sum of squares of a row is within d * 2^-24 of ||x||^2, so xm
+    // bounds every row's squared norm
+    const float xm = __uint_as_float(st->xn2max_bits) * (1.0f + (float)(d_ + 2) * 0x1p-23f);
+    const float cm = (float)(red[0] * (1.0 + 0x1p-20)) * (1.0f + 0x1p-20f);
+    // The sorted update rounds each lane's part of a point's squared distance to
+    // a multiple of 2^-FJ.  Centers of later passes are averages of rows (or kept),
+    // so ||x - c|| <= 2 max(sqrt(xm), cmax) for the whole stage: a part stays
+    // below 2^80 units and all rows' parts below 2^96.
+    int FJ = 0;
+    if (pg > 0 && !st->nonfinite) {
+      const float r = 2.0f * fmaxf(sqrtf(xm), cm) * (1.0f + 0x1p-20f);
+      const float bound = fmaxf(r * r, 0x1p-100f);
+      FJ = min(80, 96 - ceil_log2(rows)) - ilogbf(bound) - 1;
+      FJ = min(600, max(-600, FJ));
     }
-    st->FQ = FQ;
+    st->FJ = FJ;
     st->B = xm;
     st->qcount = 0u;
-    st->cmax = (float)(red[0] * (1.0 + 0x1p-20)) * (1.0f + 0x1p-20f);
+    st->cmax = cm;
     st->ticket = 0u;
     st->max_iter = max_iter;
     st->tol = tol;
@@ -518,9 +553,9 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
 }
 
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
-                       const double* cnorm, int32_t k, int32_t d, hipStream_t s) {
+                       const double* cnorm, int32_t k, int32_t d, int64_t pg, hipStream_t s) {
   hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(256), 0, s, st, max_iter, tol, rows, cnorm, k,
-                     d);
+                     d, pg);
   return hipGetLastError();
 }
 
@@ -662,7 +697,7 @@ __device__ __forceinline__ void assign_tile(
     const T* __restrict__ X, int64_t n, int d, int k, int64_t base, const float* __restrict__ cw,
     const float* __restrict__ cn, const double* __restrict__ c64, float* __restrict__ w,
     float* __restrict__ cnl, int ktile, float cmax, float scale,
-    unsigned long long* __restrict__ S, int32_t* __restrict__ labels, double& Jacc,
+    unsigned long long* __restrict__ S, int32_t* __restrict__ labels, bool wantJ, double& Jacc,
     int64_t& ucnt) {
   float x[P][DMAX];
   int64_t ip[P];
@@ -708,7 +743,7 @@ __device__ __forceinline__ void assign_tile(
   for (int p = 0; p < P; ++p) {
     if (!valid[p]) continue;
     const int l = bi[p];
-    {
+    if (wantJ) {
       const double* cl = c64 + (int64_t)l * d;
       double D = 0.0;
 #pragma unroll
@@ -796,7 +831,7 @@ __global__ __launch_bounds__(256) void k_fused(
   const int64_t tile = 256 * P;
   for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile)
     assign_tile<T, DMAX, P, false>(X, n, d, k, base, cw, cn, c64, w, cnl, k, cmax, scale,
-                                   update ? S : nullptr, labels, Jacc, ucnt);
+                                   update ? S : nullptr, labels, true, Jacc, ucnt);
   __syncthreads();
   if (update) flush_sums(S, k, d, slots);
   block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
@@ -808,7 +843,7 @@ __global__ __launch_bounds__(256) void k_assign_tiled(
     const T* __restrict__ X, int64_t n, int d, int k, int ktile, const float* __restrict__ cw,
     const float* __restrict__ cn, const double* __restrict__ c64, const PassState* __restrict__ st,
     const int32_t* __restrict__ gate, double* __restrict__ Jpart, long long* __restrict__ upart,
-    int32_t* __restrict__ labels) {
+    int32_t* __restrict__ labels, int wantJ) {
   if (gated(gate)) return;
   extern __shared__ __align__(16) unsigned char smem[];
   float* w = reinterpret_cast<float*>(smem);
@@ -819,7 +854,7 @@ __global__ __launch_bounds__(256) void k_assign_tiled(
   const int64_t tile = 256 * P;
   for (int64_t base = (int64_t)blockIdx.x * tile; base < n; base += (int64_t)gridDim.x * tile)
     assign_tile<T, DMAX, P, true>(X, n, d, k, base, cw, cn, c64, w, cnl, ktile, cmax, 1.f,
-                                  nullptr, labels, Jacc, ucnt);
+                                  nullptr, labels, wantJ != 0, Jacc, ucnt);
   block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
 }
 
@@ -830,7 +865,7 @@ __global__ __launch_bounds__(256) void k_assign_generic(
     const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cw,
     const float* __restrict__ cn, const double* __restrict__ c64, const PassState* __restrict__ st,
     const int32_t* __restrict__ gate, double* __restrict__ Jpart, long long* __restrict__ upart,
-    int32_t* __restrict__ labels) {
+    int32_t* __restrict__ labels, int wantJ) {
   if (gated(gate)) return;
   const float cmax = st->cmax;
   const float Kd = (float)(d + 2) * 0x1p-24f * 1.001f;
@@ -861,8 +896,8 @@ __global__ __launch_bounds__(256) void k_assign_generic(
     const float E = Kd * __builtin_fmaf(2.f * xn, cmax, cmax * cmax);
     const bool unc = valid && k > 1 && !((sec - best) > 2.f * E);
     ucnt += wave_fp64_fallback<T>(unc, i, X, d, k, c64, bi);
-    if (valid) {
-      labels[i] = bi;
+    if (valid) labels[i] = bi;
+    if (valid && wantJ) {
       const double* cl = c64 + (int64_t)bi * d;
       double D = 0.0;
       for (int t = 0; t < d; ++t) {
@@ -875,60 +910,225 @@ __global__ __launch_bounds__(256) void k_assign_generic(
   block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
 }
 
-// Cluster sums from labels for k*d too large for one LDS array: block (b, s, r)
-// adds dims [s*slice, ...) of the points of block b whose label lies in
-// center range r into LDS, then into the slots.  With qslots it also adds the
-// slice's part of every point's squared norm, rint(sum x^2 * 2^FQ), so that J
-// follows exactly from the cluster sums.
-template <typename T>
-__global__ __launch_bounds__(256) void k_update_split(
-    const T* __restrict__ X, const int32_t* __restrict__ labels, int64_t n, int d, int k,
-    int slice, int crange, const PassState* __restrict__ st, const int32_t* __restrict__ gate,
-    long long* __restrict__ slots, long long* __restrict__ qslots) {
+// ============================================================================
+// Cluster sums by label order, for k*d too large for LDS-private sums: a
+// counting sort of the point indices by label (chunk histograms, an exclusive
+// scan over (label, chunk), a scatter), then groups of lanes walk runs of
+// equal labels, adding whole rows in registers with the run's center at hand.
+// The sums are exact integers, so the scatter's order does not matter.
+// ============================================================================
+
+// Histogram of the labels of chunk b into cnt[j * G + b] (label-major, so an
+// exclusive scan gives each chunk's first position within label j's run).
+__global__ __launch_bounds__(256) void k_lab_count(const int32_t* __restrict__ labels, int64_t n,
+                                                   int k, int64_t chunk, int64_t G,
+                                                   long long* __restrict__ cnt,
+                                                   const int32_t* __restrict__ gate) {
   if (gated(gate)) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int t0 = blockIdx.y * slice, tw = min(slice, d - t0);
-  const int j0 = blockIdx.z * crange, jw = min(crange, k - j0);
-  unsigned long long* S = reinterpret_cast<unsigned long long*>(smem);
-  unsigned long long* Q = S + (size_t)crange * slice;
-  unsigned int* N = reinterpret_cast<unsigned int*>(Q + crange);
-  for (int e = threadIdx.x; e < jw * slice; e += 256) S[e] = 0ull;
-  for (int j = threadIdx.x; j < jw; j += 256) {
-    Q[j] = 0ull;
-    N[j] = 0u;
+  extern __shared__ uint32_t h[];
+  const int64_t b = blockIdx.x, i0 = b * chunk, i1 = min(n, i0 + chunk);
+  const bool lds = k <= kHistLds;
+  if (lds) {
+    for (int j = threadIdx.x; j < k; j += 256) h[j] = 0u;
+    __syncthreads();
   }
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const int j = labels[i];
+    if ((unsigned)j >= (unsigned)k) continue;
+    if (lds) atomicAdd(&h[j], 1u);
+    else atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[(int64_t)j * G + b]), 1ull);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < k; j += 256) cnt[(int64_t)j * G + b] = h[j];
+  }
+}
+
+// Exclusive scan of tiles of 2048 entries in place; tile totals to tot[].
+__global__ __launch_bounds__(256) void k_scan_tiles(long long* __restrict__ a, int64_t count,
+                                                    long long* __restrict__ tot,
+                                                    const int32_t* __restrict__ gate) {
+  if (gated(gate)) return;
+  __shared__ long long part[256];
+  const int64_t t0 = (int64_t)blockIdx.x * 2048 + threadIdx.x * 8;
+  long long v[8], run = 0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    v[u] = t0 + u < count ? a[t0 + u] : 0;
+    run += v[u];
+  }
+  part[threadIdx.x] = run;
   __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {  // inclusive Hillis-Steele scan of the thread sums
+    const long long add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  long long e = part[threadIdx.x] - run;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (t0 + u < count) a[t0 + u] = e;
+    e += v[u];
+  }
+  if (threadIdx.x == 255) tot[blockIdx.x] = part[255];
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(long long* __restrict__ a, int64_t count,
+                                                  const long long* __restrict__ tot,
+                                                  const int32_t* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) a[i] += tot[i >> 11];
+}
+
+// First position of every label's run: start[j] = off[j * G], start[k] = n.
+__global__ __launch_bounds__(256) void k_run_starts(const long long* __restrict__ off, int k,
+                                                    int64_t G, int64_t n,
+                                                    long long* __restrict__ start,
+                                                    const int32_t* __restrict__ gate) {
+  if (gated(gate)) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j < k) start[j] = off[(int64_t)j * G];
+  if (j == k) start[k] = n;
+}
+
+// Point indices of chunk b to their places in label order.
+__global__ __launch_bounds__(256) void k_lab_scatter(const int32_t* __restrict__ labels,
+                                                     int64_t n, int k, int64_t chunk, int64_t G,
+                                                     long long* __restrict__ off,
+                                                     uint32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ gate) {
+  if (gated(gate)) return;
+  extern __shared__ uint32_t h[];
+  const int64_t b = blockIdx.x, i0 = b * chunk, i1 = min(n, i0 + chunk);
+  const bool lds = k <= kHistLds;
+  if (lds) {
+    for (int j = threadIdx.x; j < k; j += 256) h[j] = (uint32_t)off[(int64_t)j * G + b];
+    __syncthreads();
+  }
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const int j = labels[i];
+    if ((unsigned)j >= (unsigned)k) continue;
+    const uint64_t pos =
+        lds ? (uint64_t)atomicAdd(&h[j], 1u)
+            : atomicAdd(reinterpret_cast<unsigned long long*>(&off[(int64_t)j * G + b]), 1ull);
+    perm[pos] = (uint32_t)i;
+  }
+}
+
+// The E center coordinates of a lane (FP64).
+template <int E>
+__device__ __forceinline__ void load_center(const double* __restrict__ c64, int j, int d, int col,
+                                            bool act, double (&c)[E]) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) c[e] = act ? c64[(int64_t)j * d + col + e] : 0.0;
+}
+
+// A group of G = 2^glog lanes walks positions [p0, p0 + pg) of the label order
+// (pg <= 2^13); lane gl owns the E dims at col = blockIdx.y*G*E + gl*E.  Per run
+// of equal labels it adds rint(x * 2^F) in FP64 registers (exact integers below
+// 2^43) and flushes them to slot row (group mod kSlots) with 64-bit atomics when
+// the run ends.  J: each lane's part of a point's squared distance to the run's
+// center, rounded to a multiple of 2^-FJ (below 2^80 units), is added as two
+// 40-bit limbs (exact in FP64 over 2^13 points); the group's limbs are summed
+// once at the end into jslots.  Every sum is an exact integer, so neither the
+// order of the label sort nor that of the atomics changes a bit of the result.
+template <typename T, int E>
+__global__ __launch_bounds__(256) void k_run_sums(
+    const T* __restrict__ X, int64_t n, int d, int k, int glog, int64_t pg,
+    const uint32_t* __restrict__ perm, const long long* __restrict__ start,
+    const double* __restrict__ c64, const PassState* __restrict__ st,
+    const int32_t* __restrict__ gate, long long* __restrict__ slots,
+    long long* __restrict__ jslots) {
+  if (gated(gate)) return;
+  const int G = 1 << glog;
+  const int lane = threadIdx.x & 63, gi = lane >> glog, gl = lane & (G - 1);
+  const int64_t group = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (64 >> glog) + gi;
+  // groups past the end walk nothing but still take part in the final reduction
+  const int64_t p0 = min(n, group * pg), p1 = min(n, p0 + pg);
+  const int col = (int)blockIdx.y * G * E + gl * E;
+  const bool act = col < d;  // E > 1 divides d
   const float scale = st->scale;
-  const double scaleQ = ldexp(1.0, st->FQ);
-  const bool counts = blockIdx.y == 0;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    const int l = labels[i] - j0;
-    if (l < 0 || l >= jw) continue;
-    const T* xr = X + i * d + t0;
-    double q2 = 0.0;
-    for (int tt = 0; tt < tw; ++tt) {
-      const float v = widen<T>(xr[tt]);
-      const long long q = (long long)__float2int_rn(v * scale);
-      atomicAdd(&S[(int64_t)l * slice + tt], (unsigned long long)q);
-      q2 = __builtin_fma((double)v, (double)v, q2);
+  const double sj = ldexp(1.0, st->FJ);
+  // the label of position p0: the largest j with start[j] <= p0 (start[k] = n > p0)
+  int lo = 0, hi = k;
+  while (p0 < n && hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= p0) lo = mid;
+    else hi = mid;
+  }
+  int j = lo;
+  int64_t run_end = p0 < n ? start[j + 1] : n;
+  double c[E], acc[E];
+  load_center<E>(c64, j, d, col, act && p0 < n, c);
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0;
+  double j0 = 0.0, j1 = 0.0;  // J limbs: units of 2^-FJ and of 2^(40-FJ)
+  long long cnt = 0;
+  const int slot = (int)(group & (kSlots - 1));
+  long long* srow = slots + (int64_t)slot * k * (d + 1);
+  auto flush = [&]() {
+    if (cnt == 0) return;
+    long long* row = srow + (int64_t)j * (d + 1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long long v = (long long)acc[e];
+      if (act && v) atomicAdd(reinterpret_cast<unsigned long long*>(&row[col + e]),
+                              (unsigned long long)v);
+      acc[e] = 0.0;
     }
-    if (qslots) atomicAdd(&Q[l], (unsigned long long)__double2ll_rn(q2 * scaleQ));
-    if (counts) atomicAdd(&N[l], 1u);
+    if (blockIdx.y == 0 && gl == 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&row[d]), (unsigned long long)cnt);
+    cnt = 0;
+  };
+  constexpr int R = 4;  // rows in flight per group
+  for (int64_t p = p0; p < p1; p += R) {
+    float x[R][E];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool in = p + r < p1;
+      const int64_t i = in ? (int64_t)perm[p + r] : 0;
+      load_vec<T, E>(X + i * d + col, in && act, x[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t pr = p + r;
+      if (pr < p1) {
+        if (pr >= run_end) {
+          flush();
+          do {
+            ++j;
+            run_end = start[j + 1];
+          } while (pr >= run_end);
+          load_center<E>(c64, j, d, col, act, c);
+        }
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          acc[e] += (double)rintf(x[r][e] * scale);
+          const double df = (double)x[r][e] - c[e];
+          part = part + df * df;
+        }
+        const double q = rint(part * sj);
+        const double h = floor(q * 0x1p-40);
+        j1 += h;
+        j0 += __builtin_fma(-h, 0x1p40, q);
+        ++cnt;
+      }
+    }
   }
-  __syncthreads();
-  const int slot = blockIdx.x % kSlots;
-  unsigned long long* row = reinterpret_cast<unsigned long long*>(slots + (int64_t)slot * k * (d + 1));
-  for (int e = threadIdx.x; e < jw * tw; e += 256) {
-    const int jj = e / tw, tt = e - jj * tw;
-    const unsigned long long v = S[(int64_t)jj * slice + tt];
-    if (v) atomicAdd(&row[(int64_t)(j0 + jj) * (d + 1) + t0 + tt], v);
+  flush();
+  long long l0 = (long long)j0, l1 = (long long)j1;
+  for (int o = G >> 1; o > 0; o >>= 1) {
+    l0 += __shfl_xor(l0, o);
+    l1 += __shfl_xor(l1, o);
   }
-  for (int jj = threadIdx.x; jj < jw; jj += 256) {
-    if (counts && N[jj])
-      atomicAdd(&row[(int64_t)(j0 + jj) * (d + 1) + d], (unsigned long long)N[jj]);
-    if (qslots && Q[jj])
-      atomicAdd(reinterpret_cast<unsigned long long*>(qslots + (int64_t)slot * k + j0 + jj), Q[jj]);
+  if (gl == 0 && (l0 | l1)) {
+    l1 += l0 >> 40;
+    l0 &= (1ll << 40) - 1;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&jslots[2 * slot]), (unsigned long long)l0);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&jslots[2 * slot + 1]), (unsigned long long)l1);
   }
 }
 
@@ -1552,13 +1752,13 @@ __global__ __launch_bounds__(512) void k_assign_bf16(
 // ============================================================================
 // New centers from the slot sums, stage bookkeeping
 // ============================================================================
-// Fixed-order sums of J (the assignment blocks' partials, or the per-cluster
-// values Jc when the split path derives J from the cluster sums), of the FP64
-// check counts, and (when update) the largest movement, the largest ||c|| and
+// Fixed-order sums of J (the assignment blocks' partials, or the sorted
+// update's exact limbs in jslots, which are zeroed for the next pass), of the
+// FP64 check counts, and (when update) the largest movement, the largest ||c|| and
 // the empties; then the pass bookkeeping.
 __device__ void conclude_block(PassState* __restrict__ st, const double* __restrict__ Jpart,
                                const long long* __restrict__ upart, int64_t nb,
-                               const double* __restrict__ Jc, const double* __restrict__ shiftj,
+                               long long* __restrict__ jslots, const double* __restrict__ shiftj,
                                const double* __restrict__ cnorm,
                                const int32_t* __restrict__ emptyj, int k, bool update,
                                double* __restrict__ J_hist, double* __restrict__ shift_hist) {
@@ -1568,12 +1768,10 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
   double J = 0.0, sh = 0.0, nm = 0.0;
   long long U = 0, E = 0, Pc = 0;
   for (int64_t b = tid; b < nb; b += 256) {
-    if (!Jc) J += ld_agent(&Jpart[b]);
+    if (!jslots) J += ld_agent(&Jpart[b]);
     U += ld_agent(&upart[2 * b]);
     Pc += ld_agent(&upart[2 * b + 1]);
   }
-  if (Jc)
-    for (int j = tid; j < k; j += 256) J += ld_agent(&Jc[j]);
   if (update)
     for (int j = tid; j < k; j += 256) {
       sh = fmax(sh, ld_agent(&shiftj[j]));
@@ -1594,6 +1792,19 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
     __syncthreads();
   }
   if (tid == 0) {
+    if (jslots) {
+      // the sorted update's J: exact integer limbs of 2^-FJ and 2^(40-FJ)
+      long long a0 = 0, a1 = 0;
+      for (int q = 0; q < kSlots; ++q) {
+        a0 += ld_agent(&jslots[2 * q]);
+        a1 += ld_agent(&jslots[2 * q + 1]);
+        jslots[2 * q] = 0;
+        jslots[2 * q + 1] = 0;
+      }
+      a1 += a0 >> 40;
+      a0 &= (1ll << 40) - 1;
+      rJ[0] = ldexp((double)a1, 40 - st->FJ) + ldexp((double)a0, -st->FJ);
+    }
     st->J = rJ[0];
     st->uncertain += rU[0];
     st->pairs += rP[0];
@@ -1615,14 +1826,14 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
 // One block per center: the exact sum of its kSlots slot rows (zeroed for the
 // next pass), then (update) the new center -- the average; an empty cluster
 // keeps its center -- its movement and norm, and the BF16 copy of the screen.
-// With qslots, J of the cluster follows from the sums at the pass's centers:
-// sum ||x - c||^2 = Q - 2 c.S + N ||c||^2.  The last block concludes the pass.
+// With jslots, J is that of the sorted update.  The last block concludes the
+// pass.
 __global__ __launch_bounds__(256) void k_finalize(
-    long long* __restrict__ slots, long long* __restrict__ qslots, int k, int d,
+    long long* __restrict__ slots, long long* __restrict__ jslots, int k, int d,
     PassState* __restrict__ st, const int32_t* __restrict__ gate, int update,
     double* __restrict__ c64, float* __restrict__ cw, float* __restrict__ cn,
     double* __restrict__ cnorm, double* __restrict__ shiftj, int32_t* __restrict__ emptyj,
-    double* __restrict__ S_out, int64_t* __restrict__ N_out, double* __restrict__ Jc,
+    double* __restrict__ S_out, int64_t* __restrict__ N_out,
     uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
     double* __restrict__ J_hist, double* __restrict__ shift_hist) {
@@ -1630,32 +1841,24 @@ __global__ __launch_bounds__(256) void k_finalize(
   const int j = blockIdx.x, tid = threadIdx.x;
   const int64_t C = (int64_t)k * (d + 1);
   long long* col = slots + (int64_t)j * (d + 1);
-  __shared__ long long red[256], redq[256];
-  __shared__ double rd[256], rn[256], rcs[256], rco[256];
+  __shared__ long long red[256];
+  __shared__ double rd[256], rn[256];
   __shared__ int last;
-  long long v = 0, vq = 0;
+  long long v = 0;
   if (tid < kSlots) {
     v = col[(int64_t)tid * C + d];
     col[(int64_t)tid * C + d] = 0;
-    if (qslots) {
-      vq = qslots[(int64_t)tid * k + j];
-      qslots[(int64_t)tid * k + j] = 0;
-    }
   }
   red[tid] = v;
-  redq[tid] = vq;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) {
-      red[tid] += red[tid + o];
-      redq[tid] += redq[tid + o];
-    }
+    if (tid < o) red[tid] += red[tid + o];
     __syncthreads();
   }
-  const long long Nj = red[0], Qj = redq[0];
+  const long long Nj = red[0];
   __syncthreads();
   const int F = st->F;
-  double sh = 0.0, nn = 0.0, csum = 0.0, cold2 = 0.0;
+  double sh = 0.0, nn = 0.0;
   const int r = tid & 31, c = tid >> 5;  // 32 slots x 8 dims per round
   for (int t0 = 0; t0 < d; t0 += 8) {
     const int t = t0 + c;
@@ -1672,10 +1875,8 @@ __global__ __launch_bounds__(256) void k_finalize(
     }
     if (r == 0 && t < d) {
       const double sum = ldexp((double)red[tid], -F);
-      const double cold = c64[(int64_t)j * d + t];
-      csum += cold * sum;
-      cold2 += cold * cold;
       if (update) {
+        const double cold = c64[(int64_t)j * d + t];
         const double cnew = Nj > 0 ? sum / (double)Nj : cold;
         const double diff = cnew - cold;
         sh += diff * diff;
@@ -1690,21 +1891,15 @@ __global__ __launch_bounds__(256) void k_finalize(
   }
   rd[tid] = sh;
   rn[tid] = nn;
-  rcs[tid] = csum;
-  rco[tid] = cold2;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (tid < o) {
       rd[tid] += rd[tid + o];
       rn[tid] += rn[tid + o];
-      rcs[tid] += rcs[tid + o];
-      rco[tid] += rco[tid + o];
     }
     __syncthreads();
   }
   if (tid == 0) {
-    if (qslots)  // a sum of squares: a negative value is cancellation
-      Jc[j] = fmax(0.0, ldexp((double)Qj, -st->FQ) - 2.0 * rcs[0] + (double)Nj * rco[0]);
     if (update) {
       shiftj[j] = sqrt(rd[0]);
       cn[j] = (float)rn[0];
@@ -1719,7 +1914,7 @@ __global__ __launch_bounds__(256) void k_finalize(
   __syncthreads();
   if (!last) return;
   __threadfence();
-  conclude_block(st, Jpart, upart, nb, qslots ? Jc : nullptr, shiftj, cnorm, emptyj, k,
+  conclude_block(st, Jpart, upart, nb, jslots, shiftj, cnorm, emptyj, k,
                  update != 0, J_hist, shift_hist);
   if (tid == 0) st->ticket = 0u;
 }
@@ -1896,20 +2091,12 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
         p.ktile = (int)std::max<int64_t>(1, std::min<int64_t>(k, 8192 / p.dmax));
         p.lds_assign = (size_t)p.ktile * p.dmax * 4 + (size_t)p.ktile * 4;
       }
-      // split update: crange centers x slice dims of 64-bit sums, plus crange
-      // squared-norm sums and counts, in LDS
-      int crange = k, slice;
-      if (kk * 20 > budget) {
-        crange = (int)(budget / 20);
-        slice = 1;
-      } else {
-        slice = (int)std::min<size_t>(dd, (budget - kk * 12) / (kk * 8));
-      }
-      p.crange = crange;
-      p.slice = std::max(1, slice);
-      p.nslices = (d + p.slice - 1) / p.slice;
-      p.lds_update = (size_t)crange * p.slice * 8 + (size_t)crange * 12;
-      p.ublocks = std::max<int64_t>(1, std::min<int64_t>((rows + 2047) / 2048, 1024));
+      // sorted update: label counts per chunk of points, about 2^22 (label,
+      // chunk) pairs at most; lane groups of pg positions, about 65536 groups
+      const int64_t want = (int64_t)(((double)rows * (double)k) / (double)(1 << 22)) + 1;
+      p.sort_chunk = std::max<int64_t>(4096, (want + 255) / 256 * 256);
+      p.sort_chunks = (rows + p.sort_chunk - 1) / p.sort_chunk;
+      p.pg = std::min<int64_t>(1 << 13, std::max<int64_t>(64, (rows + 65535) / 65536));
     }
   }
   // a persistent grid: no more blocks than stay resident at once
@@ -1932,33 +2119,59 @@ static void dispatch_fused(const PassBufs& b, const PassPlan& p, bool update,
 
 template <typename T>
 static void dispatch_tiled(const PassBufs& b, const PassPlan& p, const int32_t* gate,
-                           hipStream_t s) {
+                           int wantJ, hipStream_t s) {
   if (p.dmax) {
     visit_tiled<T>(p.dmax, [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
                          (const T*)b.X, b.n, b.d, b.k, p.ktile, b.cw, b.cn, b.c64,
-                         (const PassState*)b.st, gate, b.Jpart, b.upart, b.labels);
+                         (const PassState*)b.st, gate, b.Jpart, b.upart, b.labels, wantJ);
     });
   } else {
     hipLaunchKernelGGL(k_assign_generic<T>, dim3((unsigned)p.blocks), dim3(256), 0, s,
                        (const T*)b.X, b.n, b.d, b.k, b.cw, b.cn, b.c64, (const PassState*)b.st,
-                       gate, b.Jpart, b.upart, b.labels);
+                       gate, b.Jpart, b.upart, b.labels, wantJ);
   }
 }
 
-static void split_update(const PassBufs& b, const PassPlan& p, const int32_t* gate,
-                         long long* qslots, hipStream_t s) {
-  const int crange = p.crange;
-  const unsigned ncr = (unsigned)((b.k + crange - 1) / crange);
-  dim3 grid((unsigned)p.ublocks, (unsigned)p.nslices, ncr);
-  if (b.dtype == 0)
-    hipLaunchKernelGGL(k_update_split<float>, grid, dim3(256), p.lds_update, s,
-                       (const float*)b.X, (const int32_t*)b.labels, b.n, b.d, b.k, p.slice,
-                       crange, (const PassState*)b.st, gate, b.slots, qslots);
-  else
-    hipLaunchKernelGGL(k_update_split<uint16_t>, grid, dim3(256), p.lds_update, s,
-                       (const uint16_t*)b.X, (const int32_t*)b.labels, b.n, b.d, b.k, p.slice,
-                       crange, (const PassState*)b.st, gate, b.slots, qslots);
+int row_vec(int dtype, int32_t d, const void* X);
+int row_glog(int32_t d, int E);
+
+// Counting sort of the point indices by label, then the run sums.
+static void sorted_update(const PassBufs& b, const PassPlan& p, const int32_t* gate,
+                          hipStream_t s) {
+  const int64_t G = p.sort_chunks, cn = (int64_t)b.k * G;
+  const size_t lds = b.k <= kHistLds ? (size_t)b.k * 4 : 0;
+  if (!lds) (void)zero_i64(b.scnt, cn, s);
+  hipLaunchKernelGGL(k_lab_count, dim3((unsigned)G), dim3(256), lds, s, (const int32_t*)b.labels,
+                     b.n, b.k, p.sort_chunk, G, b.scnt, gate);
+  const int64_t tiles = (cn + 2047) / 2048;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(256), 0, s, b.scnt, cn, b.stot,
+                     gate);
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(256), 0, s, reinterpret_cast<int64_t*>(b.stot),
+                     tiles);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((cn + 255) / 256)), dim3(256), 0, s, b.scnt, cn,
+                     (const long long*)b.stot, gate);
+  hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((b.k + 256) / 256)), dim3(256), 0, s,
+                     (const long long*)b.scnt, b.k, G, b.n, b.rstart, gate);
+  hipLaunchKernelGGL(k_lab_scatter, dim3((unsigned)G), dim3(256), lds, s,
+                     (const int32_t*)b.labels, b.n, b.k, p.sort_chunk, G, b.scnt, b.perm, gate);
+  const int E = row_vec(b.dtype, b.d, b.X), glog = row_glog(b.d, E);
+  const int64_t groups = (b.n + p.pg - 1) / p.pg;
+  const int64_t waves = (groups + (64 >> glog) - 1) / (64 >> glog);
+  const unsigned ncb = (unsigned)((b.d + (E << glog) - 1) / (E << glog));
+  const dim3 grid((unsigned)((waves + 3) / 4), ncb);
+  auto go = [&](auto kern, auto* x) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, x, b.n, b.d, b.k, glog, p.pg,
+                       (const uint32_t*)b.perm, (const long long*)b.rstart,
+                       (const double*)b.c64, (const PassState*)b.st, gate, b.slots, b.jslots);
+  };
+  if (b.dtype == 0) {
+    if (E == 4) go(k_run_sums<float, 4>, (const float*)b.X);
+    else go(k_run_sums<float, 1>, (const float*)b.X);
+  } else {
+    if (E == 8) go(k_run_sums<uint16_t, 8>, (const uint16_t*)b.X);
+    else go(k_run_sums<uint16_t, 1>, (const uint16_t*)b.X);
+  }
 }
 
 template <typename T>
@@ -1994,8 +2207,9 @@ hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStr
     if (b.dtype == 0) dispatch_fused<float>(b, p, update, gate, s);
     else dispatch_fused<uint16_t>(b, p, update, gate, s);
   } else {
-    if (b.dtype == 0) dispatch_tiled<float>(b, p, gate, s);
-    else dispatch_tiled<uint16_t>(b, p, gate, s);
+    // an update pass takes J from the sorted update
+    if (b.dtype == 0) dispatch_tiled<float>(b, p, gate, update ? 0 : 1, s);
+    else dispatch_tiled<uint16_t>(b, p, gate, update ? 0 : 1, s);
   }
   return hipGetLastError();
 }
@@ -2003,17 +2217,19 @@ hipError_t pass_assign(const PassBufs& b, const PassPlan& p, bool update, hipStr
 hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStream_t s) {
   const int32_t* gate = update ? &b.st->done : nullptr;
   const int64_t nb = p.bf16 ? 2 * p.blocks : p.blocks;
-  // the BF16 screen leaves J to the cluster sums, so it needs them in a labelling
-  // pass too; the FP32 kernels add J per point
-  long long* qslots = p.bf16 ? b.qslots : nullptr;
   if (p.bf16) {
     if (b.dtype == 0) dispatch_rescreen<float>(b, p, gate, s);
     else dispatch_rescreen<uint16_t>(b, p, gate, s);
   }
-  if (update || p.bf16) {
-    if (!p.fused) split_update(b, p, gate, qslots, s);
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(256), 0, s, b.slots, qslots, b.k, b.d, b.st, gate, update ? 1 : 0, b.c64,
-                       b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out, b.Jc,
+  // The sorted update makes the sums of an update pass and, with the BF16
+  // screen, J of every pass; the FP32 kernels add J themselves in a labelling
+  // pass.
+  const bool sorted = !p.fused && (update || p.bf16);
+  if (sorted) sorted_update(b, p, gate, s);
+  if (update || sorted) {
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(256), 0, s, b.slots,
+                       sorted ? b.jslots : nullptr, b.k, b.d, b.st, gate, update ? 1 : 0, b.c64,
+                       b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out,
                        p.bf16 ? b.cb16 : nullptr, p.bf16 ? b.cnB : nullptr, p.ks * 16,
                        (const double*)b.Jpart, (const long long*)b.upart, nb, b.J_hist,
                        b.shift_hist);

@@ -12,6 +12,7 @@ constexpr int64_t kSelChunk = 8192;   // indices per block in the ordered compac
 constexpr int kThreads = 256;          // threads per block of the point kernels
 constexpr int kSlots = 32;             // rows of 64-bit cluster-sum slots blocks add into
 constexpr int kMaxBlocks = 4096;       // upper bound of an assignment kernel's grid
+constexpr int kHistLds = 16384;        // labels up to this count are sorted with LDS counters
 
 // Progress of one radix selection of the r smallest 64-bit keys.  When done,
 // a key is selected iff its top `bits` bits are <= prefix (keys are distinct).
@@ -35,7 +36,7 @@ struct PassState {
   uint32_t xn2max_bits;  // bits of max ||x||^2 over the stage's rows
   uint32_t ticket;     // blocks of the finalize kernel that are done (last one concludes)
   uint32_t qcount;     // points queued for the BF16 re-screen in this pass
-  int32_t FQ;          // squared norms add rint(||x_slice||^2 * 2^FQ) as 64-bit integers
+  int32_t FJ;          // the sorted update adds J in units of 2^-FJ (exact integer limbs)
   float B;             // score offset >= max ||x||^2 of the BF16 screen (keeps scores >= 0)
   int32_t nonfinite;
   int32_t empty;
@@ -59,25 +60,26 @@ hipError_t gather_rows(const void* X, int64_t nrows, int dtype, int32_t d, const
 hipError_t centers_from_rows(const void* X, int64_t nrows, int dtype, int32_t d,
                              const int64_t* idx, int32_t k, double* c64, hipStream_t s);
 hipError_t stage_reset(PassState* st, hipStream_t s);
-hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
-                     hipStream_t s);
+hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, bool norms,
+                     PassState* st, hipStream_t s);
 hipError_t zero_i64(long long* p, int64_t count, hipStream_t s);
-hipError_t row_norms(const void* X, int dtype, int64_t rows, int32_t d, PassState* st,
-                     hipStream_t s);
 hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, const PassState* st,
                      uint16_t* cb16, float* cnB, hipStream_t s);
 hipError_t prep_centers(const double* c64, int32_t k, int32_t d, float* cw, float* cn,
                         double* cnorm, hipStream_t s);
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
-                       const double* cnorm, int32_t k, int32_t d, hipStream_t s);
+                       const double* cnorm, int32_t k, int32_t d, int64_t pg, hipStream_t s);
 
 struct PassBufs {
   const void* X; int dtype; int64_t n; int32_t d; int32_t k;
   double* c64; float* cw; float* cn; double* cnorm;
   double* shiftj; int32_t* emptyj;
   long long* slots;    // [kSlots][k][d+1] exact cluster sums (counts last); zero between passes
-  long long* qslots;   // [kSlots][k] exact sums of squared norms (split path); zero between passes
-  double* Jc;          // [k] per-cluster J of the split path
+  long long* jslots;   // [kSlots][2] J of the sorted update as limbs of 2^-FJ, 2^(40-FJ); zeroed
+  uint32_t* perm;      // [n] point indices in label order (sorted update)
+  long long* scnt;     // [k * sort_chunks] label counts per chunk, then their offsets
+  long long* stot;     // [scan tiles + 1] tile totals of the offset scan
+  long long* rstart;   // [k + 1] first position of every label's run
   uint16_t* cb16;      // [k][ks*16] BF16 centers of the BF16 screen
   float* cnB;          // [k] ||c||^2 + B of the BF16 screen
   int32_t* queue;      // [n] points of the BF16 screen with more than 4 candidates
@@ -99,11 +101,10 @@ struct PassPlan {
   int dmax;          // register tile of a row (0: generic)
   int ppt;           // points per thread
   int64_t blocks;    // blocks of the assign kernel (= partial rows in the fused path)
-  int64_t ublocks;   // point blocks of the split update kernel
-  int slice;         // dims per slice of the split update
-  int nslices;
-  int crange;        // centers per range of the split update
-  size_t lds_assign, lds_update;
+  int64_t sort_chunk;   // points per chunk of the label sort (split path)
+  int64_t sort_chunks;
+  int64_t pg;           // positions per lane group of the run sums
+  size_t lds_assign;
   int ktile;         // centers per LDS tile (split assign)
 };
 

@@ -7,9 +7,8 @@ import oracle
 # Tolerances of the parity protocol: labels identical except where the oracle's
 # top-2 relative gap (D2 - D1) / D2 is below GAP; centers within CTOL relative
 # to max(||c||, rms row norm); J within JTOL relative, plus JABS * sum ||x||^2
-# absolute: the BF16 screen takes J of a cluster from its exact sums as
-# Q - 2 c.S + N ||c||^2, whose FP64 evaluation cancels down to a few ulps of
-# the terms (a cluster made of its own center gives +-1e-12, not 0).
+# absolute (a floor for fits whose J is zero: the sorted update rounds each
+# point's squared distance to units far below that).
 GAP = 1e-6
 CTOL = 1e-5
 JTOL = 1e-6

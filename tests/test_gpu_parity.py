@@ -49,7 +49,7 @@ def test_sample_matches_oracle(n, m, k, seed):
 # ------------------------------------------------------------ one-step parity
 SWEEP = [(1, 1), (1, 5), (2, 8), (3, 3), (4, 32), (5, 7), (8, 64), (16, 64), (17, 31),
          (16, 1024), (32, 8), (32, 257), (64, 64), (100, 100), (128, 2), (128, 1024),
-         (129, 16), (200, 33), (2, 2000), (8, 5000)]
+         (129, 16), (200, 33), (2, 2000), (8, 5000), (300, 40), (1000, 3)]
 
 
 @pytest.mark.parametrize("d,k", SWEEP)
@@ -330,3 +330,20 @@ def test_forced_fp32_path_on_bf16_data():
     ex = exempt_mask(Xh, C)
     assert np.array_equal(out["labels"].cpu().numpy()[~ex], ref.labels[~ex])
     assert abs(out["J"] - ref.J) <= 1e-9 * ref.J
+
+
+def test_step_more_labels_than_lds_counters():
+    """More than 16384 clusters: the label sort counts with global atomics."""
+    n, d, k = 50_000, 3, 17_000
+    Xh = _mixture(n, d, 40, seed=17)
+    C = _centers_from(Xh, k, seed=18, jitter=0.3)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    ex = exempt_mask(Xh, C)
+    lab = out["labels"].cpu().numpy()
+    assert np.array_equal(lab[~ex], ref.labels[~ex])
+    assert abs(out["J"] - ref.J) <= 1e-9 * ref.J
+    if np.array_equal(lab, ref.labels):
+        assert np.array_equal(out["N"].cpu().numpy(), ref.N)
+        assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9)
+        assert out["empty"] == ref.empty
