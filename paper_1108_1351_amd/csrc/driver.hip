@@ -173,8 +173,8 @@ Layout make_layout(const Sizes& z) {
   const size_t C = (size_t)z.k * (z.d + 1);
   L.slots = c.take<long long>((size_t)kSlots * C);
   L.jslots = c.take<long long>((size_t)kSlots * 2);
-  L.cb16 = c.take<uint16_t>(any_bf16(z) ? (size_t)z.k * 16 * ks_max(z) : 0);
-  L.cnb = c.take<float>((size_t)z.k);
+  L.cb16 = c.take<uint16_t>(any_bf16(z) ? (size_t)bf16_rows(z.k) * 16 * ks_max(z) : 0);
+  L.cnb = c.take<float>((size_t)bf16_rows(z.k));
   L.queue = c.take<int32_t>(any_bf16(z) ? (size_t)z.n : 0);
   L.qthr = c.take<float>(any_bf16(z) ? (size_t)z.n : 0);
   L.jpart = c.take<double>((size_t)blocks_max(z));
@@ -670,8 +670,8 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
                o_sh = c.take<double>(k), o_em = c.take<int32_t>(k),
                o_st = c.take<PassState>(1), o_slots = c.take<long long>((size_t)kSlots * C_),
                o_qs = c.take<long long>((size_t)kSlots * 2),
-               o_cb = c.take<uint16_t>(p.bf16 ? (size_t)k * 16 * p.ks : 0),
-               o_cnb = c.take<float>(k), o_q = c.take<int32_t>(p.bf16 ? (size_t)n : 0),
+               o_cb = c.take<uint16_t>(p.bf16 ? (size_t)bf16_rows(k) * 16 * p.ks : 0),
+               o_cnb = c.take<float>((size_t)bf16_rows(k)), o_q = c.take<int32_t>(p.bf16 ? (size_t)n : 0),
                o_qt = c.take<float>(p.bf16 ? (size_t)n : 0),
                o_jp = c.take<double>((size_t)p.blocks * 2),
                o_up = c.take<long long>((size_t)p.blocks * 4),

@@ -534,7 +534,13 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
       FJ = min(600, max(-600, FJ));
     }
     st->FJ = FJ;
-    st->B = xm;
+    // BF16 screen offset: every score ||c||^2 + B - 2 x.c stays positive, also
+    // after the screen's rounding (at most 2^-7 ||x|| ||c|| from BF16 operands
+    // and (d+8) 2^-24 of the magnitudes from FP32 accumulation)
+    {
+      const float sx = sqrtf(xm);
+      st->B = xm + 0.04f * sx * cm + (float)(d_ + 16) * 0x1p-22f * (xm + cm * cm + 2.f * sx * cm);
+    }
     st->qcount = 0u;
     st->cmax = cm;
     st->ticket = 0u;
@@ -784,11 +790,12 @@ __device__ __forceinline__ void flush_sums(const unsigned long long* __restrict_
 }
 
 // Fixed-order block sum of J (FP64) and of the FP64-check counts (full checks
-// and pair decisions; both wave-uniform).  256 threads.
+// and pair decisions; both wave-uniform), in wave order.  Up to 16 waves.
 __device__ __forceinline__ void block_sum_J(double Jacc, int64_t ucnt, int64_t pcnt,
                                             double* Jpart, long long* upart) {
-  __shared__ double wJ[4];
-  __shared__ long long wU[4], wP[4];
+  __shared__ double wJ[16];
+  __shared__ long long wU[16], wP[16];
+  const int nw = (int)(blockDim.x >> 6);  // up to 16 waves (1024 threads)
   for (int o = 32; o > 0; o >>= 1) Jacc += __shfl_xor(Jacc, o);
   if ((threadIdx.x & 63) == 0) {
     wJ[threadIdx.x >> 6] = Jacc;
@@ -797,9 +804,16 @@ __device__ __forceinline__ void block_sum_J(double Jacc, int64_t ucnt, int64_t p
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    Jpart[blockIdx.x] = ((wJ[0] + wJ[1]) + wJ[2]) + wJ[3];
-    upart[2 * blockIdx.x] = wU[0] + wU[1] + wU[2] + wU[3];
-    upart[2 * blockIdx.x + 1] = wP[0] + wP[1] + wP[2] + wP[3];
+    double J = 0.0;
+    long long U = 0, P = 0;
+    for (int w = 0; w < nw; ++w) {
+      J += wJ[w];
+      U += wU[w];
+      P += wP[w];
+    }
+    Jpart[blockIdx.x] = J;
+    upart[2 * blockIdx.x] = U;
+    upart[2 * blockIdx.x + 1] = P;
   }
 }
 
@@ -1528,15 +1542,134 @@ __device__ __forceinline__ int rerank(const T* __restrict__ xr, int d, int h, bo
   return bj;
 }
 
-// MODE 0: the points of X; each lane half keeps the best four keys of its 16
-// scores per center tile (score bits, local index in the low bits), the halves
-// merge, and the point is decided as certain, by a re-rank of the candidates
-// within the error band, or queued for MODE 1 when more than four centers lie
-// in the band.  MODE 1: the queued points; every center whose screened score
-// is within the point's threshold becomes a candidate of the re-rank.
-// 512 threads: 8 waves x PT tiles of 32 points share each center tile in LDS.
-template <typename T, int KS, int PT, int MODE>
-__global__ __launch_bounds__(512) void k_assign_bf16(
+// As rerank, for 16-byte aligned rows with d a multiple of 8: the point's row
+// and the candidate rows are read with 16-byte loads.
+template <typename T, int KS>
+__device__ __forceinline__ int rerank_vec(const T* __restrict__ xr, int d,
+                                          int h, bool active, const int* cand, int nc, int ncmax,
+                                          const float* __restrict__ cw,
+                                          const double* __restrict__ c64, float cmax,
+                                          int64_t& fp64_count) {
+  // the lane's values: dims 16 s + 8 h + e
+  auto xval = [&](int s, float (&v)[8]) {
+    if constexpr (sizeof(T) == 2) {
+      const int t0 = 16 * s + 8 * h;
+      const uint4 w = t0 < d ? *reinterpret_cast<const uint4*>(xr + t0) : make_uint4(0u, 0u, 0u, 0u);
+      const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[2 * u] = bf16_lo(w4[u]);
+        v[2 * u + 1] = bf16_hi(w4[u]);
+      }
+    } else {
+      const int t0 = 16 * s + 8 * h;
+      if (t0 < d) {
+        const float4 a = *reinterpret_cast<const float4*>(xr + t0);
+        const float4 b = *reinterpret_cast<const float4*>(xr + t0 + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = 0.f;
+      }
+    }
+  };
+  float best = INFINITY, sec = INFINITY;
+  int bj = INT_MAX;
+  for (int q = 0; q < ncmax; ++q) {
+    const int j = (active && q < nc) ? cand[q] : 0;
+    const float* cj = cw + (int64_t)j * d;
+    float part = 0.f;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int t0 = 16 * s + 8 * h;
+      if (t0 < d) {
+        float v[8];
+        xval(s, v);
+        const float4 a = *reinterpret_cast<const float4*>(cj + t0);
+        const float4 b = *reinterpret_cast<const float4*>(cj + t0 + 4);
+        const float c[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float diff = v[e] - c[e];
+          part = __builtin_fmaf(diff, diff, part);
+        }
+      }
+    }
+    const float D = part + __shfl_xor(part, 32);
+    if (active && q < nc) {
+      if (D < best || (D == best && j < bj)) {
+        sec = best;
+        best = D;
+        bj = j;
+      } else if (D < sec) {
+        sec = D;
+      }
+    }
+  }
+  const float u = 0x1p-24f * 1.01f;
+  auto err = [&](float D) { return (float)(KS * 8 + 4) * u * D + 2.f * sqrtf(D) * u * cmax + 1e-30f; };
+  const bool sure = nc <= 1 || (sec - best) > err(best) + err(sec);
+  const bool need = active && !sure;
+  if (__ballot(need)) {
+    double b64 = INFINITY;
+    int b64j = INT_MAX;
+    for (int q = 0; q < ncmax; ++q) {
+      const int j = (need && q < nc) ? cand[q] : 0;
+      const double* cj = c64 + (int64_t)j * d;
+      double part = 0.0;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int t0 = 16 * s + 8 * h;
+        if (t0 < d) {
+          float v[8];
+          xval(s, v);
+#pragma unroll
+          for (int e2 = 0; e2 < 4; ++e2) {
+            const double2 c = *reinterpret_cast<const double2*>(cj + t0 + 2 * e2);
+            const double d0 = (double)v[2 * e2] - c.x, d1 = (double)v[2 * e2 + 1] - c.y;
+            part = __builtin_fma(d0, d0, part);
+            part = __builtin_fma(d1, d1, part);
+          }
+        }
+      }
+      const double D = part + __shfl_xor(part, 32);
+      if (need && q < nc && (D < b64 || (D == b64 && j < b64j))) {
+        b64 = D;
+        b64j = j;
+      }
+    }
+    if (need) bj = b64j;
+    fp64_count += __popcll(__ballot(need && h == 0));
+  }
+  return bj;
+}
+
+// A copy of v the compiler must keep in a VGPR: with the key mask in an SGPR,
+// a key is then one v_and_or_b32 (one scalar operand per VALU instruction).
+__device__ __forceinline__ int opaque_vgpr(int v) {
+  int r;
+  asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
+// The BF16 screen of all points.  A block (4 waves) takes 4*PT tiles of 32
+// points; each wave keeps its rows as the B operand of 32x32x16 BF16 MFMAs in
+// registers.  Centers stream through LDS in stages of 128 rows, double-buffered:
+// the next stage is copied global -> LDS directly (no registers) while the
+// current one is on the matrix cores, with one barrier per stage.  A score is
+// ||c||^2 + B - 2 x.c (FP32 accumulation; B >= every ||x||^2 plus the screen's
+// error, so scores are positive and their bits order as integers).  Each lane
+// owns 16 center rows of every tile ("slots"); per pair of slots it keeps the
+// two smallest keys (score bits with the tile index and the row parity in the
+// low bits): three VALU operations per score.  At the end the lane halves merge the tracked keys;
+// a key not tracked is at least the second key of its slot pair, which bounds what
+// was not kept.  The point is certain when the best two tracked keys are
+// apart by more than the error band; re-ranked in FP32 (then FP64) when at
+// most three tracked keys lie in the band and no slot pair holds two of them; and
+// queued for the re-screen otherwise.
+template <typename T, int KS, int PT, int NW>
+__global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
     const T* __restrict__ X, int64_t n, int d, int k, const uint16_t* __restrict__ cb16,
     const float* __restrict__ cnB, const float* __restrict__ cw, const double* __restrict__ c64,
     PassState* __restrict__ st, const int32_t* __restrict__ gate, int32_t* __restrict__ labels,
@@ -1544,43 +1677,73 @@ __global__ __launch_bounds__(512) void k_assign_bf16(
     long long* __restrict__ upart) {
   if (gated(gate)) return;
   constexpr int KD = KS * 16;
-  constexpr int RS = KD + 8;      // LDS row stride in BF16 elements (spreads rows over banks)
-  constexpr int CMAX = 16;        // candidates kept per queued point
-  __shared__ __align__(16) uint16_t ctile[32 * RS];
-  __shared__ float cbias[32];
-  __shared__ int cand_n[MODE == 1 ? 8 * PT * 32 : 1];
-  __shared__ int cand_j[MODE == 1 ? 8 * PT * 32 * CMAX : 512 * 4];
+  constexpr int C8 = KD / 8;                  // 16-byte chunks per center row
+  constexpr int SW = C8 < 16 ? C8 - 1 : 15;   // chunk swizzle mask (spreads rows over banks)
+  constexpr int SC = 128;                     // center rows per stage
+  constexpr int RPI = 1024 / (KD * 2);        // rows per 1 KB LDS-direct load
+  constexpr int NI = SC / RPI;                // such loads per stage
+  // two stage buffers as separate objects, each used by its own code path, so
+  // that reads of one need not wait for the LDS-direct loads into the other
+  __shared__ __align__(16) uint16_t cb0[SC * KD], cb1[SC * KD];
+  __shared__ __align__(16) float bb0[SC], bb1[SC];
+  __shared__ int cand_j[64 * NW * 4];
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
-  const int nct = (k + 31) / 32;
+  // an even number of stages over the padded rows (padding rows score 1e30):
+  // the stage loop below runs in pairs without a branch
+  const int nst = ((k + 2 * SC - 1) / (2 * SC)) * 2, nct = nst * (SC / 32);
+  static_assert(kScreenRows % (2 * SC) == 0, "stage pairs must tile the padded rows");
+  // a key: score bits, then the tile index and the slot's row parity (TB + 1 bits)
+  int TB = 0;
+  while ((1 << TB) < nct) ++TB;
+  const int TM = (1 << (TB + 1)) - 1;
   int BG = 5;
   while ((1 << BG) < 32 * nct) ++BG;
   const int GM = (1 << BG) - 1;
   const float B = st->B, cmax = st->cmax;
-  // screen error: BF16 rounding of the centers (and of FP32 rows), 2^-8 ||x|| ||c||
-  // each, plus the FP32 accumulation of the MFMA chain
   const float eb = (sizeof(T) == 4 ? 2.f : 1.f) * 0x1p-8f * 1.01f;
   const float ea = (float)(KD + 8) * 0x1p-24f * 1.01f;
   const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
-  const int64_t count = MODE == 0 ? n : (int64_t)ld_agent(reinterpret_cast<const int32_t*>(&st->qcount));
-  const int64_t per_block = 8 * PT * 32;
+  const int64_t per_block = NW * PT * 32;
   int64_t nfull = 0, ncand = 0;
-  for (int64_t base = (int64_t)blockIdx.x * per_block; base < count;
+  // Stage g of the (padded) center rows into buffer b with LDS-direct loads:
+  // lane L of load i fills 16 bytes at row i*RPI + L/C8, position L%C8, which
+  // holds chunk (L%C8) ^ (row & SW) of that row.
+  auto issue_stage = [&](int g, uint16_t* cdst, float* bdst) {
+    for (int i = wave; i < NI; i += NW) {
+      const int row = i * RPI + lane / C8, c = (lane % C8) ^ (row & SW);
+      __builtin_amdgcn_global_load_lds(
+          static_cast<const void*>(cb16 + ((int64_t)g * SC + row) * KD + c * 8),
+          static_cast<void*>(cdst + i * RPI * KD), 16, 0, 0);
+    }
+    static_assert(SC % 64 == 0, "a stage's biases are whole 64-float loads");
+    for (int i = NW - 1 - wave; i < SC / 64; i += NW)
+      __builtin_amdgcn_global_load_lds(
+          static_cast<const void*>(cnB + (int64_t)g * SC + 64 * i + lane),
+          static_cast<void*>(bdst + 64 * i), 4, 0, 0);
+  };
+  // every wave's LDS-direct loads are in LDS before the barrier
+  auto stage_sync = [&]() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  // Blocks start at different stages (the order of the stages does not change
+  // the kept keys), so that they do not all read the same center rows from the
+  // same L2 channels at once.
+  const int rot = (int)(blockIdx.x % (unsigned)nst);
+  auto next_stage = [&](int gs) { return gs + 1 < nst ? gs + 1 : 0; };
+  if ((int64_t)blockIdx.x * per_block < n) issue_stage(rot, cb0, bb0);
+  for (int64_t base = (int64_t)blockIdx.x * per_block; base < n;
        base += (int64_t)gridDim.x * per_block) {
     v8bf x[PT][KS];
     int64_t ip[PT];
     bool valid[PT];
-    float xn[PT], thr[PT];
-    int m1[PT], m2[PT], m3[PT], m4[PT];
+    float xn[PT];
+    int m1[PT][8], m2[PT][8];  // per slot pair (rows r, r ^ 1): the two smallest keys
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
       const int64_t e = base + (int64_t)(wave * PT + p) * 32 + pc;
-      valid[p] = e < count;
-      ip[p] = 0;
-      thr[p] = 0.f;
-      if (valid[p]) {
-        ip[p] = MODE == 0 ? e : (int64_t)queue[e];
-        if (MODE == 1) thr[p] = qthr[e];
-      }
+      valid[p] = e < n;
+      ip[p] = valid[p] ? e : 0;
       float s2 = 0.f;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
@@ -1594,8 +1757,194 @@ __global__ __launch_bounds__(512) void k_assign_bf16(
         }
       }
       xn[p] = sqrtf(s2 + __shfl_xor(s2, 32)) * 1.01f;
-      m1[p] = m2[p] = m3[p] = m4[p] = INT_MAX;
-      if (MODE == 1 && h == 0) cand_n[(wave * PT + p) * 32 + pc] = 0;
+#pragma unroll
+      for (int g = 0; g < 8; ++g) m1[p][g] = m2[p][g] = INT_MAX;
+    }
+    // the 32-center tiles of stage gs, read from one buffer
+    auto compute_stage = [&](int gs, const uint16_t* cbuf, const float* bbuf) {
+#pragma unroll 1
+      for (int t = 0; t < SC / 32; ++t) {
+        const int ct = gs * (SC / 32) + t;
+        {
+          v16f bias;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) bias[r] = bbuf[t * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
+          const int row = t * 32 + pc;
+          v8bf a[KS];
+#pragma unroll
+          for (int s = 0; s < KS; ++s)
+            a[s] = *reinterpret_cast<const v8bf*>(&cbuf[row * KD + (((2 * s + h) ^ (row & SW)) * 8)]);
+          v16f acc[PT];
+#pragma unroll
+          for (int p = 0; p < PT; ++p)
+            acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], x[p][0], bias, 0, 0, 0);
+#pragma unroll
+          for (int s = 1; s < KS; ++s)
+#pragma unroll
+            for (int p = 0; p < PT; ++p)
+              acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], x[p][s], acc[p], 0, 0, 0);
+          const int vc0 = opaque_vgpr(ct << 1), vc1 = opaque_vgpr((ct << 1) | 1);
+#pragma unroll
+          for (int p = 0; p < PT; ++p)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int kv = (__float_as_int(acc[p][r]) & ~TM) | ((r & 1) ? vc1 : vc0);
+              m2[p][r >> 1] = med3_i32(m1[p][r >> 1], kv, m2[p][r >> 1]);
+              m1[p][r >> 1] = min(m1[p][r >> 1], kv);
+            }
+        }
+      }
+    };
+    stage_sync();
+    // stages in pairs: buffer 0 holds stages 0, 2, ..., buffer 1 stages 1, 3, ...;
+    // each stage's successor loads into the other buffer while it computes
+    int gs = rot;
+    for (int g = 0; g < nst; g += 2) {
+      const int gs1 = next_stage(gs), gs2 = next_stage(gs1);
+      issue_stage(gs1, cb1, bb1);
+      compute_stage(gs, cb0, bb0);
+      stage_sync();
+      if (g + 2 < nst) issue_stage(gs2, cb0, bb0);
+      compute_stage(gs1, cb1, bb1);
+      stage_sync();
+      gs = gs2;
+    }
+    // both buffers are free: the next tile's first stage loads during the re-rank
+    if (base + (int64_t)gridDim.x * per_block < n) issue_stage(rot, cb0, bb0);
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const float E2 = 2.f * (eb * xn[p] * cmax + ea * (cmax * cmax + B + 2.f * xn[p] * cmax));
+      // tracked keys -> global keys (value bits above BG, center index below)
+      int g4[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+      int mm2 = INT_MAX;
+      auto insert = [&](int kv) {
+        g4[3] = med3_i32(g4[2], kv, g4[3]);
+        g4[2] = med3_i32(g4[1], kv, g4[2]);
+        g4[1] = med3_i32(g4[0], kv, g4[1]);
+        g4[0] = min(g4[0], kv);
+      };
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        // rows 2g, 2g+1 of the lane: center offset 8(g/2) + 4h + 2(g%2) + parity
+        const int off = 8 * (g >> 1) + 4 * h + 2 * (g & 1);
+        auto glob = [&](int a) {
+          return a == INT_MAX ? INT_MAX
+                              : ((a & ~GM) | (32 * ((a & TM) >> 1) + off + (a & 1)));
+        };
+        const int ga = glob(m1[p][g]), gb = glob(m2[p][g]);
+        insert(ga);
+        insert(gb);
+        mm2 = min(mm2, gb);
+      }
+      int o[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) o[u] = __shfl_xor(g4[u], 32);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) insert(o[u]);
+      mm2 = min(mm2, __shfl_xor(mm2, 32));
+      float v[4];
+      int jj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[u] = g4[u] == INT_MAX ? INFINITY : __int_as_float(g4[u] & ~GM);
+        jj[u] = g4[u] == INT_MAX ? INT_MAX : (g4[u] & GM);
+      }
+      const float vm2 = mm2 == INT_MAX ? INFINITY : __int_as_float(mm2 & ~GM);
+      auto apart = [&](float a, float b) {
+        return (b - a) > E2 + delta * (fabsf(a) + fabsf(b));
+      };
+      const int* cand = nullptr;
+      int nc = 0, label = 0;
+      bool full = false, decided = false;
+      if (k == 1 || (jj[0] < k && apart(v[0], v[1]))) {
+        decided = true;
+        label = jj[0] < k ? jj[0] : 0;
+      } else if (jj[0] < k && (k <= 4 || (apart(v[0], v[3]) && apart(v[0], vm2)))) {
+        int* mine = &cand_j[threadIdx.x * 4];
+        mine[nc++] = jj[0];
+#pragma unroll
+        for (int u = 1; u < 4; ++u)
+          if (jj[u] < k && !apart(v[0], v[u])) mine[nc++] = jj[u];
+        cand = mine;
+      } else {
+        full = true;
+      }
+      const bool q = valid[p] && full && h == 0;
+      const unsigned long long bq = __ballot(q);
+      if (bq) {
+        unsigned base_q = 0;
+        if (lane == 0) base_q = atomicAdd(&st->qcount, (unsigned)__popcll(bq));
+        base_q = __shfl(base_q, 0);
+        if (q) {
+          const unsigned pos = base_q + __popcll(bq & ((1ull << lane) - 1ull));
+          queue[pos] = (int32_t)ip[p];
+          qthr[pos] = v[0] + E2 + 4.f * delta * (fabsf(v[0]) + E2) + 1e-30f;
+        }
+      }
+      nfull += __popcll(bq);
+      if (!valid[p]) {
+        decided = true;
+        nc = 0;
+      }
+      int ncmax = nc;
+      for (int o2 = 32; o2 > 0; o2 >>= 1) ncmax = max(ncmax, __shfl_xor(ncmax, o2));
+      const bool rr = !decided && !full && nc > 0;
+      if (ncmax > 0) {
+        const int lab =
+            ((d & 7) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0)
+                ? rerank_vec<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax,
+                                    ncand)
+                : rerank<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax, ncand);
+        if (rr) label = lab;
+      }
+      if (valid[p] && h == 0 && !full) labels[ip[p]] = label < k ? label : 0;
+    }
+  }
+  block_sum_J(0.0, nfull, ncand, Jpart, upart);
+}
+
+// The re-screen of the points the screen queued: every center whose screened
+// score is at most the point's threshold becomes a candidate (up to CMAX; more
+// send the point to the FP64 check over all centers), then the candidates are
+// re-ranked as in the screen.  512 threads: 8 waves x PT tiles of 32 points
+// share each 32-center tile in LDS.
+template <typename T, int KS, int PT>
+__global__ __launch_bounds__(512) void k_rescreen_bf16(
+    const T* __restrict__ X, int d, int k, const uint16_t* __restrict__ cb16,
+    const float* __restrict__ cnB, const float* __restrict__ cw, const double* __restrict__ c64,
+    PassState* __restrict__ st, const int32_t* __restrict__ gate, int32_t* __restrict__ labels,
+    const int32_t* __restrict__ queue, const float* __restrict__ qthr,
+    double* __restrict__ Jpart, long long* __restrict__ upart) {
+  if (gated(gate)) return;
+  constexpr int KD = KS * 16;
+  constexpr int RS = KD + 8;      // LDS row stride in BF16 elements (spreads rows over banks)
+  constexpr int CMAX = 16;        // candidates kept per queued point
+  __shared__ __align__(16) uint16_t ctile[32 * RS];
+  __shared__ float cbias[32];
+  __shared__ int cand_n[8 * PT * 32];
+  __shared__ int cand_j[8 * PT * 32 * CMAX];
+  const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
+  const int nct = (k + 31) / 32;
+  const float cmax = st->cmax;
+  const int64_t count = (int64_t)ld_agent(reinterpret_cast<const int32_t*>(&st->qcount));
+  const int64_t per_block = 8 * PT * 32;
+  const bool vec = (d & 7) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  int64_t nfull = 0, ncand = 0;
+  for (int64_t base = (int64_t)blockIdx.x * per_block; base < count;
+       base += (int64_t)gridDim.x * per_block) {
+    v8bf x[PT][KS];
+    int64_t ip[PT];
+    bool valid[PT];
+    float thr[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int64_t e = base + (int64_t)(wave * PT + p) * 32 + pc;
+      valid[p] = e < count;
+      ip[p] = valid[p] ? (int64_t)queue[e] : 0;
+      thr[p] = valid[p] ? qthr[e] : 0.f;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) x[p][s] = load8_bf16<T>(X + ip[p] * d, 16 * s + 8 * h, d, valid[p]);
+      if (h == 0) cand_n[(wave * PT + p) * 32 + pc] = 0;
     }
     for (int ct = 0; ct < nct; ++ct) {
       __syncthreads();
@@ -1622,128 +1971,46 @@ __global__ __launch_bounds__(512) void k_assign_bf16(
       for (int s = 0; s < KS; ++s) {
         const v8bf a = *reinterpret_cast<const v8bf*>(&ctile[pc * RS + 16 * s + 8 * h]);
 #pragma unroll
-        for (int p = 0; p < PT; ++p) acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, x[p][s], acc[p], 0, 0, 0);
-      }
-      if constexpr (MODE == 0) {
-        const int lbase = ct << 4;  // local index 16 ct + r, monotone in the center index
-#pragma unroll
         for (int p = 0; p < PT; ++p)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int kv = (__float_as_int(acc[p][r]) & ~GM) | (lbase + r);
-            m4[p] = med3_i32(m3[p], kv, m4[p]);
-            m3[p] = med3_i32(m2[p], kv, m3[p]);
-            m2[p] = med3_i32(m1[p], kv, m2[p]);
-            m1[p] = min(m1[p], kv);
-          }
-      } else {
-#pragma unroll
-        for (int p = 0; p < PT; ++p)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            if (valid[p] && acc[p][r] <= thr[p]) {
-              const int j = ct * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-              const int slot = (wave * PT + p) * 32 + pc;
-              const int q = atomicAdd(&cand_n[slot], 1);
-              if (q < CMAX && j < k) cand_j[slot * CMAX + q] = j;
-            }
-          }
+          acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, x[p][s], acc[p], 0, 0, 0);
       }
+#pragma unroll
+      for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if (valid[p] && acc[p][r] <= thr[p]) {
+            const int j = ct * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+            const int slot = (wave * PT + p) * 32 + pc;
+            const int q = atomicAdd(&cand_n[slot], 1);
+            if (q < CMAX && j < k) cand_j[slot * CMAX + q] = j;
+          }
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-      const float E2 = 2.f * (eb * xn[p] * cmax + ea * (cmax * cmax + B + 2.f * xn[p] * cmax));
-      const int* cand = nullptr;
-      int nc = 0;
-      bool full = false, decided = false;
+      const int slot = (wave * PT + p) * 32 + pc;
+      const int cn_ = cand_n[slot];
+      // more candidates than the list holds (or, defensively, none): FP64 over
+      // all centers
+      const bool full = valid[p] && (cn_ > CMAX || cn_ == 0);
+      const int nc = (valid[p] && !full) ? cn_ : 0;
+      const int* cand = &cand_j[slot * CMAX];
       int label = 0;
-      if constexpr (MODE == 0) {
-        // lane-local index -> center index, then merge the two halves
-        int g[4] = {m1[p], m2[p], m3[p], m4[p]};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int l = g[u] & GM;
-          g[u] = (g[u] & ~GM) | (32 * (l >> 4) + 8 * ((l & 15) >> 2) + 4 * h + (l & 3));
-        }
-        int o[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) o[u] = __shfl_xor(g[u], 32);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          g[3] = med3_i32(g[2], o[u], g[3]);
-          g[2] = med3_i32(g[1], o[u], g[2]);
-          g[1] = med3_i32(g[0], o[u], g[1]);
-          g[0] = min(g[0], o[u]);
-        }
-        float v[4];
-        int jj[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          v[u] = __int_as_float(g[u] & ~GM);
-          jj[u] = g[u] & GM;
-        }
-        auto apart = [&](float a, float b) {
-          return (b - a) > E2 + delta * (fabsf(a) + fabsf(b));
-        };
-        if (k == 1 || (jj[0] < k && apart(v[0], v[1]))) {
-          decided = true;
-          label = jj[0] < k ? jj[0] : 0;
-        } else if (jj[0] < k && (k <= 4 || apart(v[0], v[3]))) {
-          int* mine = &cand_j[threadIdx.x * 4];
-          mine[nc++] = jj[0];
-#pragma unroll
-          for (int u = 1; u < 4; ++u)
-            if (jj[u] < k && !apart(v[0], v[u])) mine[nc++] = jj[u];
-          cand = mine;
-        } else {
-          full = true;
-        }
-        // queue: every center whose score is within the band of the best
-        const bool q = valid[p] && full && h == 0;
-        const unsigned long long bq = __ballot(q);
-        if (bq) {
-          unsigned base_q = 0;
-          if (lane == 0) base_q = atomicAdd(&st->qcount, (unsigned)__popcll(bq));
-          base_q = __shfl(base_q, 0);
-          if (q) {
-            const unsigned pos = base_q + __popcll(bq & ((1ull << lane) - 1ull));
-            queue[pos] = (int32_t)ip[p];
-            qthr[pos] = v[0] + E2 + 4.f * delta * (fabsf(v[0]) + E2) + 1e-30f;
-          }
-        }
-        nfull += __popcll(bq);
-      } else {
-        const int slot = (wave * PT + p) * 32 + pc;
-        const int cn_ = cand_n[slot];
-        if (cn_ > CMAX) {
-          full = true;  // more candidates than the list holds: FP64 over all centers
-        } else {
-          nc = cn_;
-          cand = &cand_j[slot * CMAX];
-        }
-      }
-      if (!valid[p]) {
-        decided = true;
-        nc = 0;
-      }
       int ncmax = nc;
       for (int o = 32; o > 0; o >>= 1) ncmax = max(ncmax, __shfl_xor(ncmax, o));
-      const bool rr = !decided && !full && nc > 0;
       if (ncmax > 0) {
-        const int lab = rerank<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax,
-                                      ncand);
+        const bool rr = nc > 0;
+        const int lab =
+            vec ? rerank_vec<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax, ncand)
+                : rerank<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax, ncand);
         if (rr) label = lab;
       }
-      if (MODE == 1) {
-        // overflowing lists: all centers in FP64, cooperatively across the wave
-        const bool ovf = valid[p] && full;
-        int lab2 = label;
-        nfull += wave_fp64_fallback<T>(ovf && h == 0, ip[p], X, d, k, c64, lab2);
-        lab2 = __shfl(lab2, pc);
-        if (ovf) label = lab2;
-      }
-      if (valid[p] && h == 0 && (MODE == 1 || !full)) labels[ip[p]] = label < k ? label : 0;
+      int lab2 = label;
+      nfull += wave_fp64_fallback<T>(full && h == 0, ip[p], X, d, k, c64, lab2);
+      lab2 = __shfl(lab2, pc);
+      if (full) label = lab2;
+      if (valid[p] && h == 0) labels[ip[p]] = label < k ? label : 0;
     }
   }
   block_sum_J(0.0, nfull, ncand, Jpart, upart);
@@ -1935,17 +2202,18 @@ __global__ __launch_bounds__(64) void k_prep_bf16(const double* __restrict__ c64
   const int j = blockIdx.x, lane = threadIdx.x;
   double acc = 0.0;
   for (int t = lane; t < kd16; t += 64) {
-    const double c = t < d ? c64[(int64_t)j * d + t] : 0.0;
+    const double c = (t < d && j < k) ? c64[(int64_t)j * d + t] : 0.0;
     cb16[(int64_t)j * kd16 + t] = f32_to_bf16((float)(-2.0 * c));
     acc += c * c;
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) cnB[j] = (float)(acc + (double)st->B);
+  if (lane == 0) cnB[j] = j < k ? (float)(acc + (double)st->B) : 1e30f;
 }
 
 hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, const PassState* st,
                      uint16_t* cb16, float* cnB, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep_bf16, dim3(k), dim3(64), 0, s, c64, k, d, kd16, st, cb16, cnB);
+  hipLaunchKernelGGL(k_prep_bf16, dim3((unsigned)bf16_rows(k)), dim3(64), 0, s, c64, k, d, kd16,
+                     st, cb16, cnB);
   return hipGetLastError();
 }
 
@@ -2028,14 +2296,28 @@ static int64_t resident_blocks(K kernel, size_t lds, int cus, int threads = 256)
   return (int64_t)nb * std::max(1, cus);
 }
 
-template <typename T, int MODE, typename F>
-static void visit_bf16(int ks, F&& f) {
+// Screen kernel for ks 16-dim K steps: PT point tiles per wave, NW waves a block.
+template <typename T, typename F>
+static void visit_screen(int ks, F&& f) {
   switch (ks) {
-    case 1: f(k_assign_bf16<T, 1, 2, MODE>); break;
-    case 2: f(k_assign_bf16<T, 2, 2, MODE>); break;
-    case 4: f(k_assign_bf16<T, 4, 2, MODE>); break;
-    case 8: f(k_assign_bf16<T, 8, 2, MODE>); break;
-    default: f(k_assign_bf16<T, 16, 1, MODE>); break;
+    case 1: f(k_screen_bf16<T, 1, 2, 4>); break;
+    case 2: f(k_screen_bf16<T, 2, 2, 4>); break;
+    case 4: f(k_screen_bf16<T, 4, 1, 8>); break;
+    case 8: f(k_screen_bf16<T, 8, 2, 4>); break;
+    default: f(k_screen_bf16<T, 16, 1, 8>); break;
+  }
+}
+constexpr int screen_threads(int ks) { return (ks == 4 || ks >= 16) ? 512 : 256; }
+constexpr int kScreenPoints = 256;  // points per block and tile (NW * PT * 32)
+
+template <typename T, typename F>
+static void visit_rescreen(int ks, F&& f) {
+  switch (ks) {
+    case 1: f(k_rescreen_bf16<T, 1, 2>); break;
+    case 2: f(k_rescreen_bf16<T, 2, 2>); break;
+    case 4: f(k_rescreen_bf16<T, 4, 2>); break;
+    case 8: f(k_rescreen_bf16<T, 8, 2>); break;
+    default: f(k_rescreen_bf16<T, 16, 1>); break;
   }
 }
 
@@ -2043,7 +2325,9 @@ template <typename T>
 static int64_t plan_blocks(const PassPlan& p, int cus) {
   int64_t r = 0;
   auto f = [&](auto kern) { r = resident_blocks(kern, p.lds_assign, cus); };
-  if (p.bf16) visit_bf16<T, 0>(p.ks, [&](auto kern) { r = resident_blocks(kern, 0, cus, 512); });
+  if (p.bf16)
+    visit_screen<T>(p.ks,
+                    [&](auto kern) { r = resident_blocks(kern, 0, cus, screen_threads(p.ks)); });
   else if (p.mfma) visit_mfma<T>(p.kd, p.nt, f);
   else if (p.fused) visit_fused<T>(p.dmax, f);
   else if (p.dmax) visit_tiled<T>(p.dmax, f);
@@ -2070,7 +2354,7 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   const size_t lds_fused = ((kk * (size_t)p.dmax + kk) * 4 + 15) / 16 * 16 + kk * (dd + 1) * 8;
   int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
   if (p.bf16) {
-    work = (rows + 511) / 512;
+    work = (rows + kScreenPoints - 1) / kScreenPoints;
   } else if (d <= 32 && k <= 128 && lds_mfma <= budget) {
     p.mfma = true;
     p.fused = true;
@@ -2177,8 +2461,9 @@ static void sorted_update(const PassBufs& b, const PassPlan& p, const int32_t* g
 template <typename T>
 static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* gate,
                           hipStream_t s) {
-  visit_bf16<T, 0>(p.ks, [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(512), 0, s, (const T*)b.X, b.n, b.d,
+  visit_screen<T>(p.ks, [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(screen_threads(p.ks)), 0, s,
+                       (const T*)b.X, b.n, b.d,
                        b.k, (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
                        (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr, b.Jpart,
                        b.upart);
@@ -2190,11 +2475,11 @@ static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* g
 template <typename T>
 static void dispatch_rescreen(const PassBufs& b, const PassPlan& p, const int32_t* gate,
                               hipStream_t s) {
-  visit_bf16<T, 1>(p.ks, [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(512), 0, s, (const T*)b.X, b.n, b.d,
-                       b.k, (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
-                       (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr,
-                       b.Jpart + p.blocks, b.upart + 2 * p.blocks);
+  visit_rescreen<T>(p.ks, [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(512), 0, s, (const T*)b.X, b.d, b.k,
+                       (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
+                       (const double*)b.c64, b.st, gate, b.labels, (const int32_t*)b.queue,
+                       (const float*)b.qthr, b.Jpart + p.blocks, b.upart + 2 * p.blocks);
   });
 }
 

@@ -13,6 +13,12 @@ constexpr int kThreads = 256;          // threads per block of the point kernels
 constexpr int kSlots = 32;             // rows of 64-bit cluster-sum slots blocks add into
 constexpr int kMaxBlocks = 4096;       // upper bound of an assignment kernel's grid
 constexpr int kHistLds = 16384;        // labels up to this count are sorted with LDS counters
+constexpr int kScreenRows = 256;       // BF16 center rows are padded to a multiple of this
+
+// Rows of the BF16 screen's center copy: k padded with zero rows whose bias is huge.
+inline int64_t bf16_rows(int32_t k) {
+  return ((int64_t)k + kScreenRows - 1) / kScreenRows * kScreenRows;
+}
 
 // Progress of one radix selection of the r smallest 64-bit keys.  When done,
 // a key is selected iff its top `bits` bits are <= prefix (keys are distinct).
@@ -80,8 +86,8 @@ struct PassBufs {
   long long* scnt;     // [k * sort_chunks] label counts per chunk, then their offsets
   long long* stot;     // [scan tiles + 1] tile totals of the offset scan
   long long* rstart;   // [k + 1] first position of every label's run
-  uint16_t* cb16;      // [k][ks*16] BF16 centers of the BF16 screen
-  float* cnB;          // [k] ||c||^2 + B of the BF16 screen
+  uint16_t* cb16;      // [bf16_rows(k)][ks*16] BF16 (-2 c) of the BF16 screen, zero padded
+  float* cnB;          // [bf16_rows(k)] ||c||^2 + B of the BF16 screen (1e30 on padding rows)
   int32_t* queue;      // [n] points of the BF16 screen with more than 4 candidates
   float* qthr;         // [n] their score thresholds
   double* Jpart; long long* upart;
