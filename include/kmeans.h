@@ -164,6 +164,91 @@ typedef struct {
 km_status kmeans_profile_begin(void);
 km_status kmeans_profile_end(km_prof* out);
 
+/* ---------------------------------------------------------------------------
+ * Many independent problems at once.  Each request is the two-stage method of
+ * kmeans_fit on its own data; the passes of all requests advance together,
+ * one launch per kernel for all of them (a batched pass), so that many small
+ * problems share the GPU instead of each paying its own launches.  The batched
+ * path scores distances in FP32 with the same certified error bound and FP64
+ * check as kmeans_fit's FP32 kernels (for FP32 and BF16 data alike), keeps
+ * exact 64-bit integer cluster sums, and supports d <= 128.  Its register tile
+ * (points per thread, centers per LDS tile) comes from a built-in autotuner,
+ * measured once per (dtype, d bucket, k bucket) and cached for the process.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const void* X;          /* n*d elements, row-major: device memory, or host memory with */
+  int32_t x_on_host;      /*   x_on_host = 1 (serving only; the server copies it)         */
+  km_dtype dtype;
+  int64_t n;
+  int32_t d;
+  int32_t k;
+  double subset_frac;     /* as kmeans_fit */
+  uint64_t seed;
+  int32_t max_iter[2];    /* fast, slow stage */
+  double tol[2];
+  float* centers_out;     /* DEVICE k*d FP32, written when the problem completes */
+  int32_t* labels_out;    /* DEVICE n int32, or NULL */
+} km_request;
+
+typedef struct {
+  km_status status;       /* KM_OK, or the problem's own error (others still complete) */
+  km_info info;           /* seconds[] and fp64_pairs are not filled by the batched path */
+  double queue_seconds;   /* serving: submit -> admission */
+  double run_seconds;     /* admission (or call start) -> results in place */
+} km_result;
+
+/* Fits count problems.  X, centers_out and labels_out are device pointers
+   (x_on_host must be 0).  results: host, count entries.  Returns KM_OK when
+   every problem was attempted; per-problem errors are in results[i].status.
+   Blocks until all results are in place.  stream: hipStream_t or NULL. */
+km_status kmeans_fit_batch(const km_request* reqs, int32_t count, km_result* results,
+                           void* stream);
+
+/* The autotuner's choice for a problem shape: points per thread of the
+   batched assignment and centers per LDS tile (a problem with fewer centers
+   uses k of them).  Tunes on first use of the (dtype, d, k) bucket. */
+km_status km_tune_query(km_dtype dtype, int32_t d, int32_t k, int32_t* points_per_thread,
+                        int32_t* centers_per_tile);
+
+/* ---------------------------------------------------------------------------
+ * Serving.  A server owns a scheduler thread and a HIP stream on the device
+ * current at creation.  Submitted problems wait in a queue until their device
+ * footprint (a copy of X, centers, labels, sums and sampling buffers) fits in
+ * the budget next to the admitted ones; admitted problems advance together in
+ * batched passes, and problems that arrive while others run join at the next
+ * pass (continuous batching).  Results are bit-identical to the same request
+ * run alone (exact sums, fixed-order J).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  size_t hbm_budget_bytes;  /* device memory for admitted problems (0: 3/4 of free memory) */
+  int32_t max_active;       /* problems advanced together, <= 8192 (0: 4096) */
+  int32_t max_pending;      /* submitted, not yet admitted (0: 1 << 20); beyond: KM_EBUSY */
+  int32_t use_graphs;       /* 1: replay captured HIP graphs of the batched pass */
+} km_server_cfg;
+
+typedef struct {
+  int64_t submitted, admitted, completed, failed;
+  int64_t rounds;              /* batched passes launched */
+  int64_t active, pending;     /* now */
+  size_t bytes_in_use, peak_bytes;
+  int64_t peak_active;
+} km_server_counters;
+
+typedef struct km_server km_server;
+
+km_status km_server_create(const km_server_cfg* cfg, km_server** out);
+/* Queues a copy of the request and returns at once with a ticket.  The server
+   copies X into its own device buffer when it admits the problem, so X (host or
+   device) and the output pointers must stay valid until km_server_wait returns
+   for the ticket. */
+km_status km_server_submit(km_server* srv, const km_request* req, uint64_t* ticket);
+/* Waits up to timeout_us (< 0: forever) for the ticket's result; KM_ETIMEOUT
+   leaves it pending, KM_ENOTFOUND for an unknown or already collected ticket. */
+km_status km_server_wait(km_server* srv, uint64_t ticket, km_result* out, int64_t timeout_us);
+km_status km_server_stats(km_server* srv, km_server_counters* out);
+/* Stops the scheduler; unfinished problems complete with KM_ECANCELLED. */
+km_status km_server_destroy(km_server* srv);
+
 /* Return the device memory the library keeps for reuse between calls. */
 km_status kmeans_release_memory(void);
 

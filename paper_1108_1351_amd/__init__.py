@@ -23,7 +23,9 @@ KM_F32, KM_BF16 = 0, 1
 PRECISION = {"auto": 0, "fp32": 1, "bf16_rerank": 2}
 EXPORTS = ("kmeans_fit", "kmeans_fit_ex", "kmeans_default_options", "kmeans_workspace_bytes",
            "km_sample", "km_step", "km_assign", "kmeans_last_error", "kmeans_profile_begin",
-           "kmeans_profile_end", "kmeans_release_memory")
+           "kmeans_profile_end", "kmeans_release_memory", "kmeans_fit_batch", "km_tune_query",
+           "km_server_create", "km_server_submit", "km_server_wait", "km_server_stats",
+           "km_server_destroy")
 
 
 class KMeansError(RuntimeError):
@@ -65,6 +67,35 @@ class km_prof(ctypes.Structure):
                 "assign_ms": list(self.assign_ms), "pass_ms": list(self.pass_ms)}
 
 
+class km_request(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("x_on_host", ctypes.c_int32), ("dtype", ctypes.c_int),
+                ("n", ctypes.c_int64), ("d", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("subset_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("max_iter", ctypes.c_int32 * 2), ("tol", ctypes.c_double * 2),
+                ("centers_out", ctypes.c_void_p), ("labels_out", ctypes.c_void_p)]
+
+
+class km_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("info", km_info), ("queue_seconds", ctypes.c_double),
+                ("run_seconds", ctypes.c_double)]
+
+
+class km_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("max_pending", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+
+
+class km_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("pending", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t),
+                ("peak_bytes", ctypes.c_size_t), ("peak_active", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -97,8 +128,17 @@ def load():
     lib.kmeans_release_memory.argtypes = []
     lib.kmeans_last_error.argtypes = []
     lib.kmeans_last_error.restype = ctypes.c_char_p
+    lib.kmeans_fit_batch.argtypes = [P(km_request), i32, P(km_result), vp]
+    lib.km_tune_query.argtypes = [ctypes.c_int, i32, i32, P(i32), P(i32)]
+    lib.km_server_create.argtypes = [P(km_server_cfg), P(vp)]
+    lib.km_server_submit.argtypes = [vp, P(km_request), P(u64)]
+    lib.km_server_wait.argtypes = [vp, u64, P(km_result), i64]
+    lib.km_server_stats.argtypes = [vp, P(km_server_counters)]
+    lib.km_server_destroy.argtypes = [vp]
     for name in ("kmeans_fit", "kmeans_fit_ex", "km_sample", "km_step", "km_assign",
-                 "kmeans_profile_begin", "kmeans_profile_end", "kmeans_release_memory"):
+                 "kmeans_profile_begin", "kmeans_profile_end", "kmeans_release_memory",
+                 "kmeans_fit_batch", "km_tune_query", "km_server_create", "km_server_submit",
+                 "km_server_wait", "km_server_stats", "km_server_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -273,3 +313,112 @@ def kmeans_profile_end() -> dict:
 
 def kmeans_release_memory() -> None:
     _check(load().kmeans_release_memory())
+
+
+def _request(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter, tol,
+             C: torch.Tensor, L, on_host: bool) -> km_request:
+    n, d = X.shape
+    if not X.is_contiguous():
+        raise ValueError("X must be contiguous")
+    if not on_host and not X.is_cuda:
+        raise ValueError("X must be a device tensor")
+    r = km_request()
+    r.X = X.data_ptr()
+    r.x_on_host = int(on_host)
+    r.dtype = _dtype_code(X)
+    r.n, r.d, r.k = n, d, k
+    r.subset_frac, r.seed = subset_frac, seed
+    mi, tl = _pair(max_iter), _pair(tol)
+    r.max_iter[0], r.max_iter[1] = int(mi[0]), int(mi[1])
+    r.tol[0], r.tol[1] = float(tl[0]), float(tl[1])
+    r.centers_out = C.data_ptr()
+    r.labels_out = L.data_ptr() if L is not None else None
+    return r
+
+
+def _result_dict(res: km_result) -> dict:
+    out = res.info.as_dict()
+    out.update(status=res.status, queue_seconds=res.queue_seconds, run_seconds=res.run_seconds)
+    return out
+
+
+def kmeans_fit_batch(problems, labels: bool = True, stream=None):
+    """Many independent two-stage fits advanced together (C: kmeans_fit_batch).
+
+    problems: sequence of (X, k, subset_frac, seed, max_iter, tol) with X a device
+    tensor (FP32 or BF16, d <= 128).  Returns a list of (centers, labels, info)
+    per problem; info["status"] is the problem's own status (0 = ok).
+    """
+    lib = load()
+    reqs = (km_request * max(1, len(problems)))()
+    res = (km_result * max(1, len(problems)))()
+    outs = []
+    for i, (X, k, f, seed, mi, tl) in enumerate(problems):
+        n, d = X.shape
+        C = torch.empty((k, d), dtype=torch.float32, device=X.device)
+        L = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
+        reqs[i] = _request(X, k, f, seed, mi, tl, C, L, False)
+        outs.append((C, L))
+    _check(lib.kmeans_fit_batch(reqs, len(problems), res, _stream(stream)))
+    return [(C, L, _result_dict(res[i])) for i, (C, L) in enumerate(outs)]
+
+
+def km_tune_query(dtype, d: int, k: int):
+    """(points per thread, centers per LDS tile) the autotuner picks for a shape."""
+    code = KM_F32 if dtype in (torch.float32, KM_F32, "f32") else KM_BF16
+    ppt, kt = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().km_tune_query(code, d, k, ctypes.byref(ppt), ctypes.byref(kt)))
+    return ppt.value, kt.value
+
+
+class Server:
+    """A serving loop (C: km_server_*): problems are admitted by device-memory
+    footprint and advance together in batched passes; submit returns a ticket."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_active: int = 0, max_pending: int = 0,
+                 use_graphs: bool = True):
+        cfg = km_server_cfg()
+        cfg.hbm_budget_bytes, cfg.max_active = hbm_budget_bytes, max_active
+        cfg.max_pending, cfg.use_graphs = max_pending, int(use_graphs)
+        self._h = ctypes.c_void_p()
+        _check(load().km_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._outs = {}
+
+    def submit(self, X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter=50,
+               tol=1e-4, labels: bool = True, device="cuda") -> int:
+        n, d = X.shape
+        C = torch.empty((k, d), dtype=torch.float32, device=device)
+        L = torch.empty(n, dtype=torch.int32, device=device) if labels else None
+        if X.is_cuda:
+            torch.cuda.current_stream().synchronize()  # X is complete before the server copies it
+        r = _request(X, k, subset_frac, seed, max_iter, tol, C, L, not X.is_cuda)
+        t = ctypes.c_uint64()
+        _check(load().km_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        self._outs[t.value] = (C, L, X)  # X stays alive until the result is collected
+        return t.value
+
+    def wait(self, ticket: int, timeout: float | None = None):
+        res = km_result()
+        us = -1 if timeout is None else int(timeout * 1e6)
+        rc = load().km_server_wait(self._h, ticket, ctypes.byref(res), us)
+        if rc == KM_ETIMEOUT:
+            raise TimeoutError(kmeans_last_error())
+        C, L, _ = self._outs.pop(ticket, (None, None, None))
+        _check(rc)
+        return C, L, _result_dict(res)
+
+    def stats(self) -> dict:
+        c = km_server_counters()
+        _check(load().km_server_stats(self._h, ctypes.byref(c)))
+        return c.as_dict()
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().km_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

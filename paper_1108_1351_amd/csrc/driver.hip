@@ -19,89 +19,12 @@
 #include <vector>
 
 #include "../../include/kmeans.h"
+#include "host_common.h"
 #include "km_internal.h"
 
 using namespace km;
 
 namespace {
-
-thread_local std::string g_err;
-
-km_status fail(km_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-km_status fail(km_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_err = buf;
-  return st;
-}
-
-#define HIP_TRY(call)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess) {                                                             \
-      rc = fail(KM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));             \
-      goto done;                                                                        \
-    }                                                                                   \
-  } while (0)
-
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
-      .count();
-}
-
-int device_cus() {
-  static std::mutex mu;
-  static std::vector<int> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  std::lock_guard<std::mutex> lk(mu);
-  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
-  if (!cache[dev]) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        v <= 0)
-      v = 256;
-    cache[dev] = v;
-  }
-  return cache[dev];
-}
-
-size_t device_lds_limit() {
-  static std::mutex mu;
-  static std::vector<size_t> cache;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 65536;
-  std::lock_guard<std::mutex> lk(mu);
-  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
-  if (!cache[dev]) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-        v <= 0)
-      v = 65536;
-    cache[dev] = (size_t)v;
-  }
-  // leave room for the kernels' static LDS
-  return cache[dev] > 2048 ? cache[dev] - 2048 : cache[dev];
-}
-
-int64_t subset_size(int64_t n, int32_t k, double f) {
-  int64_t m = (int64_t)std::floor(f * (double)n + 0.5);
-  return std::min<int64_t>(n, std::max<int64_t>(k, m));
-}
-
-// Sub-allocations of one device block, 256-byte aligned.
-struct Carver {
-  size_t off = 0;
-  template <typename T>
-  size_t take(size_t count) {
-    size_t o = off;
-    off += (count * sizeof(T) + 255) / 256 * 256;
-    return o;
-  }
-};
 
 struct Layout {
   size_t sel, hist, blk, sub, init_sel, init_key, xs, c64, cw, cn, cnorm, shiftj, emptyj, st,
@@ -189,77 +112,6 @@ Layout make_layout(const Sizes& z) {
   L.bytes = c.off;
   return L;
 }
-
-template <typename T>
-T* at(void* base, size_t off) {
-  return reinterpret_cast<T*>(static_cast<unsigned char*>(base) + off);
-}
-
-bool valid_common(int64_t n, int32_t d, int32_t k) {
-  if (n < 1) return !fail(KM_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
-  if (d < 1) return !fail(KM_EINVAL, "d must be >= 1 (got %d)", d);
-  if (k < 1) return !fail(KM_EINVAL, "k must be >= 1 (got %d)", k);
-  if (n > INT64_MAX / d) return !fail(KM_EINVAL, "n*d overflows int64");
-  if ((int64_t)k * (d + 1) > (1LL << 31)) return !fail(KM_EINVAL, "k*(d+1) too large");
-  return true;
-}
-
-// Per-device stream-ordered pool that keeps freed blocks for reuse, so the
-// workspace of repeated calls costs no new device mapping.
-std::mutex g_pool_mu;
-std::vector<hipMemPool_t> g_pools;
-
-hipMemPool_t device_pool() {
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(g_pool_mu);
-  if ((int)g_pools.size() <= dev) g_pools.resize(dev + 1, nullptr);
-  if (!g_pools[dev]) {
-    hipMemPoolProps props;
-    memset(&props, 0, sizeof props);
-    props.allocType = hipMemAllocationTypePinned;
-    props.location.type = hipMemLocationTypeDevice;
-    props.location.id = dev;
-    hipMemPool_t pool = nullptr;
-    if (hipMemPoolCreate(&pool, &props) != hipSuccess) return nullptr;
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    g_pools[dev] = pool;
-  }
-  return g_pools[dev];
-}
-
-// Device memory for one call: the caller's workspace or a stream-ordered allocation.
-struct DevMem {
-  void* ptr = nullptr;
-  bool owned = false;
-  hipStream_t s = nullptr;
-  km_status get(size_t bytes, void* ws, size_t ws_bytes, hipStream_t st) {
-    s = st;
-    if (ws) {
-      if (ws_bytes < bytes)
-        return fail(KM_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
-                    bytes);
-      ptr = ws;
-      return KM_OK;
-    }
-    hipMemPool_t pool = device_pool();
-    hipError_t e = pool ? hipMallocFromPoolAsync(&ptr, std::max<size_t>(bytes, 256), pool, st)
-                        : hipMallocAsync(&ptr, std::max<size_t>(bytes, 256), st);
-    if (e != hipSuccess) {
-      ptr = nullptr;
-      return fail(KM_ENOMEM, "device allocation of %zu bytes failed: %s", bytes,
-                  hipGetErrorString(e));
-    }
-    owned = true;
-    return KM_OK;
-  }
-  ~DevMem() {
-    if (owned && ptr) {
-      (void)hipFreeAsync(ptr, s);
-    }
-  }
-};
 
 // Event timing of the passes (kmeans_profile_begin / _end).
 struct Prof {

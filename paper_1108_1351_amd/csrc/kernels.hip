@@ -792,7 +792,9 @@ __device__ __forceinline__ void flush_sums(const unsigned long long* __restrict_
 // Fixed-order block sum of J (FP64) and of the FP64-check counts (full checks
 // and pair decisions; both wave-uniform), in wave order.  Up to 16 waves.
 __device__ __forceinline__ void block_sum_J(double Jacc, int64_t ucnt, int64_t pcnt,
-                                            double* Jpart, long long* upart) {
+                                            double* Jpart, long long* upart,
+                                            int64_t idx = -1) {
+  if (idx < 0) idx = blockIdx.x;
   __shared__ double wJ[16];
   __shared__ long long wU[16], wP[16];
   const int nw = (int)(blockDim.x >> 6);  // up to 16 waves (1024 threads)
@@ -811,10 +813,11 @@ __device__ __forceinline__ void block_sum_J(double Jacc, int64_t ucnt, int64_t p
       U += wU[w];
       P += wP[w];
     }
-    Jpart[blockIdx.x] = J;
-    upart[2 * blockIdx.x] = U;
-    upart[2 * blockIdx.x + 1] = P;
+    Jpart[idx] = J;
+    upart[2 * idx] = U;
+    upart[2 * idx + 1] = P;
   }
+  __syncthreads();  // wJ/wU/wP may be reused by a following call
 }
 
 // Fused pass for small k*d: assignment, J and LDS-private cluster sums; each
@@ -2028,7 +2031,8 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
                                long long* __restrict__ jslots, const double* __restrict__ shiftj,
                                const double* __restrict__ cnorm,
                                const int32_t* __restrict__ emptyj, int k, bool update,
-                               double* __restrict__ J_hist, double* __restrict__ shift_hist) {
+                               double* __restrict__ J_hist, double* __restrict__ shift_hist,
+                               bool mark_labelled = false) {
   __shared__ double rJ[256], rS[256], rN[256];
   __shared__ long long rU[256], rE[256], rP[256];
   const int tid = threadIdx.x;
@@ -2086,6 +2090,8 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
       st->iter = it + 1;
       st->converged = rS[0] < st->tol ? 1 : 0;
       st->done = (st->converged || it + 1 >= st->max_iter) ? 1 : 0;
+    } else if (mark_labelled) {
+      st->done = 2;  // a batched labelling pass ran; later launches skip it
     }
   }
 }
@@ -2095,17 +2101,15 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
 // keeps its center -- its movement and norm, and the BF16 copy of the screen.
 // With jslots, J is that of the sorted update.  The last block concludes the
 // pass.
-__global__ __launch_bounds__(256) void k_finalize(
-    long long* __restrict__ slots, long long* __restrict__ jslots, int k, int d,
-    PassState* __restrict__ st, const int32_t* __restrict__ gate, int update,
-    double* __restrict__ c64, float* __restrict__ cw, float* __restrict__ cn,
-    double* __restrict__ cnorm, double* __restrict__ shiftj, int32_t* __restrict__ emptyj,
-    double* __restrict__ S_out, int64_t* __restrict__ N_out,
+__device__ void finalize_center(
+    int j, long long* __restrict__ slots, long long* __restrict__ jslots, int k, int d,
+    PassState* __restrict__ st, int update, double* __restrict__ c64, float* __restrict__ cw,
+    float* __restrict__ cn, double* __restrict__ cnorm, double* __restrict__ shiftj,
+    int32_t* __restrict__ emptyj, double* __restrict__ S_out, int64_t* __restrict__ N_out,
     uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
-    double* __restrict__ J_hist, double* __restrict__ shift_hist) {
-  if (gated(gate)) return;
-  const int j = blockIdx.x, tid = threadIdx.x;
+    double* __restrict__ J_hist, double* __restrict__ shift_hist, bool mark_labelled = false) {
+  const int tid = threadIdx.x;
   const int64_t C = (int64_t)k * (d + 1);
   long long* col = slots + (int64_t)j * (d + 1);
   __shared__ long long red[256];
@@ -2179,11 +2183,27 @@ __global__ __launch_bounds__(256) void k_finalize(
     last = atomicAdd(&st->ticket, 1u) == (unsigned)(k - 1) ? 1 : 0;
   }
   __syncthreads();
-  if (!last) return;
-  __threadfence();
-  conclude_block(st, Jpart, upart, nb, jslots, shiftj, cnorm, emptyj, k,
-                 update != 0, J_hist, shift_hist);
-  if (tid == 0) st->ticket = 0u;
+  if (last) {
+    __threadfence();
+    conclude_block(st, Jpart, upart, nb, jslots, shiftj, cnorm, emptyj, k, update != 0, J_hist,
+                   shift_hist, mark_labelled);
+    if (tid == 0) st->ticket = 0u;
+  }
+  __syncthreads();  // the shared arrays may be reused by a following call
+}
+
+__global__ __launch_bounds__(256) void k_finalize(
+    long long* __restrict__ slots, long long* __restrict__ jslots, int k, int d,
+    PassState* __restrict__ st, const int32_t* __restrict__ gate, int update,
+    double* __restrict__ c64, float* __restrict__ cw, float* __restrict__ cn,
+    double* __restrict__ cnorm, double* __restrict__ shiftj, int32_t* __restrict__ emptyj,
+    double* __restrict__ S_out, int64_t* __restrict__ N_out,
+    uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
+    const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
+    double* __restrict__ J_hist, double* __restrict__ shift_hist) {
+  if (gated(gate)) return;
+  finalize_center(blockIdx.x, slots, jslots, k, d, st, update, c64, cw, cn, cnorm, shiftj, emptyj,
+                  S_out, N_out, cb16, cnB, kd16, Jpart, upart, nb, J_hist, shift_hist);
 }
 
 // J and FP64-check counts of a labelling pass of the fused paths.  One block.
@@ -2192,6 +2212,125 @@ __global__ __launch_bounds__(256) void k_sum_J(PassState* __restrict__ st,
                                                const long long* __restrict__ upart, int64_t nb) {
   conclude_block(st, Jpart, upart, nb, nullptr, nullptr, nullptr, nullptr, 0, false, nullptr,
                  nullptr);
+}
+
+// ============================================================================
+// Many instances per launch
+// ============================================================================
+// The instance owning entry u: the last one whose first entry is <= u (every
+// listed instance has at least one entry).
+__device__ __forceinline__ int batch_find(const BatchInst* __restrict__ bi, int ninst, int64_t u,
+                                          bool centers) {
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    const int64_t s0 = centers ? bi[mid].center0 : bi[mid].unit0;
+    if (s0 <= u) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// One launch assigns the points of every listed instance: each work unit is a
+// tile of P*256 points of one instance, centers staged through LDS by ktile,
+// FP32 scores certified against their error bound (FP64 otherwise), J per
+// point in FP64, and (Lloyd passes) exact cluster sums, privatised in LDS when
+// they fit or added with 64-bit atomics into the instance's slot rows.
+// Persistent: blocks loop over the units.
+template <typename T, int DMAX, int P>
+__global__ __launch_bounds__(256) void k_batch_assign(const BatchHead* __restrict__ hd,
+                                                      const BatchInst* __restrict__ bi) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ninst = hd->ninst;
+  const int64_t units = hd->units;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const BatchInst& b = bi[batch_find(bi, ninst, u, false)];
+    PassState* st = b.st;
+    const int dn = ld_agent(&st->done);
+    if ((b.mode == 1 && dn) || (b.mode == 2 && dn == 2)) continue;
+    const int64_t tile = u - b.unit0;
+    const int d = b.d, k = b.k, ktile = b.ktile;
+    float* w = reinterpret_cast<float*>(smem);
+    float* cnl = w + (size_t)ktile * DMAX;
+    unsigned long long* S = nullptr;
+    const bool lds = b.mode == 1 && b.lds_sums;
+    const int slot = (int)(tile & (kSlots - 1));
+    unsigned long long* row =
+        reinterpret_cast<unsigned long long*>(b.slots + (int64_t)slot * k * (d + 1));
+    if (lds) {
+      S = reinterpret_cast<unsigned long long*>(
+          smem + (((size_t)ktile * (DMAX + 1) * 4 + 15) / 16) * 16);
+      for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
+      __syncthreads();
+    } else if (b.mode == 1) {
+      S = row;
+    }
+    double Jacc = 0.0;
+    int64_t ucnt = 0;
+    assign_tile<T, DMAX, P, true>(reinterpret_cast<const T*>(b.X), b.n, d, k,
+                                  tile * (int64_t)(P * 256), b.cw, b.cn, b.c64, w, cnl, ktile,
+                                  st->cmax, st->scale, S, b.labels, true, Jacc, ucnt);
+    if (lds) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < k * (d + 1); e += 256) {
+        const unsigned long long v = S[e];
+        if (v) atomicAdd(&row[e], v);
+      }
+    }
+    block_sum_J(Jacc, ucnt, 0, b.Jpart, b.upart, tile);
+  }
+}
+
+// Finalize entries of every listed instance (one per center), persistent.  The
+// last entry of an instance concludes its pass (J, movement, stop test).
+__global__ __launch_bounds__(256) void k_batch_finalize(const BatchHead* __restrict__ hd,
+                                                        const BatchInst* __restrict__ bi) {
+  const int ninst = hd->ninst;
+  const int64_t centers = hd->centers;
+  for (int64_t c = blockIdx.x; c < centers; c += gridDim.x) {
+    const BatchInst& b = bi[batch_find(bi, ninst, c, true)];
+    const int dn = ld_agent(&b.st->done);
+    if ((b.mode == 1 && dn) || (b.mode == 2 && dn == 2)) continue;
+    finalize_center((int)(c - b.center0), b.slots, nullptr, b.k, b.d, b.st, b.mode == 1 ? 1 : 0,
+                    b.c64, b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, nullptr, nullptr, nullptr,
+                    nullptr, 0, b.Jpart, b.upart, b.units, b.J_hist, b.shift_hist, b.mode == 2);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batch_status(const BatchHead* __restrict__ hd,
+                                                      const BatchInst* __restrict__ bi,
+                                                      BatchStatus* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= hd->ninst) return;
+  const PassState* st = bi[i].st;
+  BatchStatus r;
+  r.done = st->done;
+  r.iter = st->iter;
+  r.converged = st->converged;
+  r.empty = st->empty;
+  r.nonfinite = st->nonfinite;
+  r.pad = 0;
+  r.J = st->J;
+  r.shift = st->shift;
+  r.uncertain = st->uncertain;
+  out[i] = r;
+}
+
+// Uniform values in [-1, 1) from a counter-based hash (autotuning data), as
+// FP32 (kind 0), BF16 bits (1) or FP64 (2).
+__global__ __launch_bounds__(256) void k_fill_uniform(void* __restrict__ p, int64_t count,
+                                                      uint64_t seed, int kind) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double v = (double)(z >> 11) * 0x1p-52 - 1.0;
+    if (kind == 0) static_cast<float*>(p)[i] = (float)v;
+    else if (kind == 1) static_cast<uint16_t*>(p)[i] = f32_to_bf16((float)v);
+    else static_cast<double*>(p)[i] = v;
+  }
 }
 
 // BF16 copy of -2 c (dims padded with zeros to kd16) and ||c||^2 + B.
@@ -2522,6 +2661,60 @@ hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStrea
     hipLaunchKernelGGL(k_sum_J, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
                        (const long long*)b.upart, nb);
   }
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- batched
+int batch_dmax(int32_t d) { return pick_dmax(d); }
+
+// Register tiles of the batched assignment: points per thread for each dmax.
+template <typename T, typename F>
+static bool visit_batch(int dmax, int ppt, F&& f) {
+#define KM_BATCH(DM, PP)                  \
+  if (dmax == DM && ppt == PP) {          \
+    f(k_batch_assign<T, DM, PP>);         \
+    return true;                          \
+  }
+  KM_BATCH(2, 2) KM_BATCH(2, 4) KM_BATCH(4, 2) KM_BATCH(4, 4) KM_BATCH(8, 2) KM_BATCH(8, 4)
+  KM_BATCH(16, 1) KM_BATCH(16, 2) KM_BATCH(32, 1) KM_BATCH(64, 1) KM_BATCH(128, 1)
+#undef KM_BATCH
+  return false;
+}
+
+int64_t batch_resident_blocks(int dtype, int dmax, int ppt, size_t lds, int cus) {
+  int64_t r = 0;
+  auto f = [&](auto kern) { r = resident_blocks(kern, lds, cus); };
+  const bool ok = dtype == 0 ? visit_batch<float>(dmax, ppt, f) : visit_batch<uint16_t>(dmax, ppt, f);
+  return ok ? r : 0;
+}
+
+hipError_t batch_assign(const BatchHead* hd, const BatchInst* bi, const BatchShape& sh,
+                        hipStream_t s) {
+  auto f = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)sh.blocks), dim3(256), sh.lds, s, hd, bi);
+  };
+  const bool ok = sh.dtype == 0 ? visit_batch<float>(sh.dmax, sh.ppt, f)
+                                : visit_batch<uint16_t>(sh.dmax, sh.ppt, f);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t batch_finalize(const BatchHead* hd, const BatchInst* bi, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_finalize, dim3((unsigned)std::max(1, blocks)), dim3(256), 0, s, hd,
+                     bi);
+  return hipGetLastError();
+}
+
+hipError_t batch_status(const BatchHead* hd, const BatchInst* bi, BatchStatus* out,
+                        hipStream_t s) {
+  // up to 65536 instances per table
+  hipLaunchKernelGGL(k_batch_status, dim3(256), dim3(256), 0, s, hd, bi, out);
+  return hipGetLastError();
+}
+
+hipError_t fill_uniform(void* p, int kind, int64_t count, uint64_t seed, hipStream_t s) {
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_fill_uniform, dim3(g), dim3(256), 0, s, p, count, seed, kind);
   return hipGetLastError();
 }
 

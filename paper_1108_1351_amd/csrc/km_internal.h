@@ -55,6 +55,41 @@ struct PassState {
   int64_t rows;
 };
 
+// One instance of a batched pass: many independent k-means problems advance
+// together, one launch per kernel for all of them (device-resident; filled by
+// the host).  Work units are tiles of points; finalize entries are centers.
+struct BatchInst {
+  const void* X;
+  int64_t n;
+  int32_t d, k;
+  int32_t dtype;     // 0 FP32, 1 BF16
+  int32_t mode;      // 0 idle, 1 Lloyd pass (assign + update), 2 labelling pass
+  int32_t lds_sums;  // 1: cluster sums privatised in LDS, 0: atomics into the slot rows
+  int32_t ktile;     // centers per LDS tile of the assignment
+  int64_t unit0, units;  // its work units in the assignment grid (tiles of tile_pts points)
+  int64_t tile_pts;
+  int64_t center0;       // its first entry in the finalize grid (k entries)
+  double* c64; float* cw; float* cn; double* cnorm; double* shiftj; int32_t* emptyj;
+  PassState* st;
+  long long* slots;      // [kSlots][k][d+1]
+  int32_t* labels;       // [n]
+  double* Jpart;         // [units]
+  long long* upart;      // [2 * units]
+  double* J_hist; double* shift_hist;  // optional, indexed by the pass
+};
+struct BatchHead {
+  int32_t ninst;
+  int32_t pad;
+  int64_t units;    // sum of the instances' units (assignment) ...
+  int64_t centers;  // ... and of their k (finalize)
+};
+// Compact per-instance status after a batched pass, for the host scheduler.
+struct BatchStatus {
+  int32_t done, iter, converged, empty, nonfinite, pad;
+  double J, shift;
+  int64_t uncertain;
+};
+
 // Launch helpers (kernels.hip).  All return hipSuccess or the launch error.
 hipError_t sel_run(const int64_t* idx_arr, int64_t count, uint64_t seed, int64_t r,
                    SelState* st, unsigned long long* hist, int64_t* blk, int64_t* out,
@@ -113,6 +148,23 @@ struct PassPlan {
   size_t lds_assign;
   int ktile;         // centers per LDS tile (split assign)
 };
+
+// Batched passes (kernels.hip).  A group shares the element type and the
+// register tile (dmax, points per thread); bi/hd are device pointers.
+struct BatchShape {
+  int dtype, dmax, ppt;
+  size_t lds;   // dynamic LDS of the assignment launch
+  int blocks;   // persistent grid
+};
+int batch_dmax(int32_t d);                       // 0: d too large for the batched path
+int64_t batch_resident_blocks(int dtype, int dmax, int ppt, size_t lds, int cus);
+hipError_t batch_assign(const BatchHead* hd, const BatchInst* bi, const BatchShape& sh,
+                        hipStream_t s);
+hipError_t batch_finalize(const BatchHead* hd, const BatchInst* bi, int blocks, hipStream_t s);
+hipError_t batch_status(const BatchHead* hd, const BatchInst* bi, BatchStatus* out,
+                        hipStream_t s);
+// uniform [-1, 1) values: kind 0 FP32, 1 BF16 bits, 2 FP64
+hipError_t fill_uniform(void* p, int kind, int64_t count, uint64_t seed, hipStream_t s);
 
 PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
                    size_t lds_limit, int cus);

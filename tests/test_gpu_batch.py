@@ -1,0 +1,157 @@
+"""Batched fits and the serving loop against the FP64 oracle, through the C ABI.
+
+kmeans_fit_batch advances many independent two-stage fits in shared launches;
+each problem must still match the oracle run on its own data (iterations,
+centers, J, labels).  The server admits problems by device-memory footprint
+and batches their passes as they arrive; a problem's result must be the same
+bits alone and in a mix.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_helpers import JTOL, assert_centers, assert_labels, j_atol, to_device
+
+pytestmark = pytest.mark.gpu
+
+km = pytest.importorskip("paper_1108_1351_amd")
+
+
+def _problem(n, d, k, seed, dtype):
+    spec = synth.MixtureSpec(d, max(2, k // 2), "uniform", -15.0, 15.0, sigma_lo=0.5,
+                             sigma_hi=2.0, weights="dirichlet1")
+    return synth.generate(spec, seed, n, dtype)
+
+
+# (n, d, k, dtype, subset_frac, seed, max_iter, tol)
+PROBLEMS = [
+    (3_000, 2, 4, "f32", 0.05, 1, (30, 30), (1e-4, 1e-4)),
+    (20_011, 8, 16, "f32", 0.02, 2, (20, 25), (1e-3, 1e-5)),
+    (1_000, 3, 7, "f32", 0.5, 3, (40, 40), (0.0, 0.0)),
+    (5_003, 32, 64, "bf16", 0.1, 4, (10, 10), (1e-4, 1e-4)),
+    (12_000, 128, 100, "bf16", 0.05, 5, (6, 8), (1e-4, 1e-4)),
+    (40_000, 16, 256, "f32", 0.01, 6, (8, 8), (1e-4, 1e-4)),   # sums by global atomics
+    (700, 64, 9, "f32", 1.0, 7, (15, 15), (1e-6, 1e-6)),
+]
+
+
+def _check_against_oracle(Xh, C, L, info, k, f, seed, mi, tl, name):
+    ref = oracle.fit(Xh, k, f, seed, mi, tl)
+    assert info["status"] == 0, name
+    assert info["m"] == ref.info["m"], name
+    assert info["iters"] == ref.info["iters"], (name, info["iters"], ref.info["iters"])
+    assert info["converged"] == ref.info["converged"], name
+    assert info["dist_evals"] == ref.info["dist_evals"], name
+    assert_centers(C.cpu().numpy().astype(np.float64), ref.centers, Xh, tol=1e-5, name=name)
+    assert abs(info["J"] - ref.info["J"]) <= JTOL * ref.info["J"] + j_atol(Xh), name
+    assert abs(info["J_stage1"] - ref.info["J_stage1"]) <= JTOL * ref.info["J_stage1"] + j_atol(Xh)
+    assert_labels(L, Xh, ref.centers, ref_labels=ref.labels, name=name)
+
+
+def test_fit_batch_matches_oracle_per_problem():
+    data = [_problem(n, d, k, 100 + s, dt) for (n, d, k, dt, f, s, mi, tl) in PROBLEMS]
+    probs = [(to_device(Xh), k, f, s, mi, tl)
+             for Xh, (n, d, k, dt, f, s, mi, tl) in zip(data, PROBLEMS)]
+    print(f"[batch] {len(probs)} problems", flush=True)
+    out = km.kmeans_fit_batch(probs)
+    for Xh, (C, L, info), (n, d, k, dt, f, s, mi, tl) in zip(data, out, PROBLEMS):
+        _check_against_oracle(Xh, C, L, info, k, f, s, mi, tl, f"n={n} d={d} k={k} {dt}")
+
+
+def test_fit_batch_one_bad_problem_others_complete():
+    Xa = _problem(2_000, 4, 5, 11, "f32")
+    Xb = _problem(50, 4, 5, 12, "f32")
+    probs = [(to_device(Xa), 5, 0.1, 1, 20, 1e-4), (to_device(Xb), 60, 0.5, 1, 20, 1e-4)]
+    out = km.kmeans_fit_batch(probs)
+    assert out[1][2]["status"] == km.KM_EINVAL
+    _check_against_oracle(Xa, out[0][0], out[0][1], out[0][2], 5, 0.1, 1, (20, 20),
+                          (1e-4, 1e-4), "good problem")
+
+
+def test_fit_batch_many_small_problems():
+    rng = np.random.default_rng(9)
+    specs = []
+    for i in range(40):
+        n = int(rng.integers(300, 4000))
+        d = int(rng.choice([2, 8, 32]))
+        k = int(rng.integers(2, 24))
+        specs.append((n, d, k, "f32" if d < 32 else "bf16", 0.2, 1000 + i, (15, 15),
+                      (1e-4, 1e-4)))
+    data = [_problem(n, d, k, s, dt) for (n, d, k, dt, f, s, mi, tl) in specs]
+    out = km.kmeans_fit_batch([(to_device(Xh), k, f, s, mi, tl)
+                               for Xh, (n, d, k, dt, f, s, mi, tl) in zip(data, specs)])
+    for Xh, (C, L, info), (n, d, k, dt, f, s, mi, tl) in zip(data, out, specs):
+        _check_against_oracle(Xh, C, L, info, k, f, s, mi, tl, f"n={n} d={d} k={k}")
+
+
+def test_tune_query_returns_a_valid_tile():
+    for d, k in [(2, 8), (8, 100), (32, 256), (128, 64)]:
+        ppt, kt = km.km_tune_query(torch.float32, d, k)
+        assert ppt in (1, 2, 4) and kt in (32, 64, 128, 256)
+
+
+def _serve_one(srv, Xh, k, f, seed, mi, tl):
+    t = srv.submit(torch.from_numpy(Xh.view(np.int16) if Xh.dtype == np.uint16 else Xh)
+                   .view(torch.bfloat16 if Xh.dtype == np.uint16 else torch.float32),
+                   k, f, seed, mi, tl)
+    return t
+
+
+def test_server_result_same_alone_and_in_mix():
+    target = (_problem(30_000, 8, 24, 77, "f32"), 24, 0.02, 5, (25, 25), (1e-4, 1e-4))
+    Xh, k, f, seed, mi, tl = target
+    with km.Server() as srv:
+        t = _serve_one(srv, Xh, k, f, seed, mi, tl)
+        C0, L0, info0 = srv.wait(t, timeout=120)
+    rng = np.random.default_rng(3)
+    others = [(_problem(int(rng.integers(500, 20000)), int(d), int(rng.integers(3, 40)), 500 + i,
+                        "f32" if d < 32 else "bf16"))
+              for i, d in enumerate(rng.choice([2, 8, 32, 128], size=24))]
+    with km.Server() as srv:
+        tickets = []
+        for i, Xo in enumerate(others[:12]):
+            tickets.append(_serve_one(srv, Xo, min(16, len(Xo) // 10), 0.1, i, (10, 10),
+                                      (1e-4, 1e-4)))
+        t = _serve_one(srv, Xh, k, f, seed, mi, tl)
+        for i, Xo in enumerate(others[12:]):
+            tickets.append(_serve_one(srv, Xo, min(16, len(Xo) // 10), 0.1, 12 + i, (10, 10),
+                                      (1e-4, 1e-4)))
+        C1, L1, info1 = srv.wait(t, timeout=120)
+        for tt in tickets:
+            srv.wait(tt, timeout=120)
+        st = srv.stats()
+    assert st["completed"] == 25 and st["failed"] == 0
+    assert torch.equal(C0, C1)
+    assert torch.equal(L0, L1)
+    assert info0["J"] == info1["J"] and info0["iters"] == info1["iters"]
+    _check_against_oracle(Xh, C1, L1, info1, k, f, seed, mi, tl, "served")
+
+
+def test_server_admission_respects_budget():
+    probs = [(_problem(20_000, 8, 8, 900 + i, "f32"), 8) for i in range(6)]
+    with km.Server() as probe:
+        t = _serve_one(probe, probs[0][0], 8, 0.1, 0, 10, 1e-4)
+        probe.wait(t, timeout=60)
+        one = probe.stats()["peak_bytes"]
+    budget = int(one * 2.5)  # room for two problems at a time
+    with km.Server(hbm_budget_bytes=budget) as srv:
+        ts = [_serve_one(srv, Xh, k, 0.1, i, 10, 1e-4) for i, (Xh, k) in enumerate(probs)]
+        res = [srv.wait(t, timeout=120) for t in ts]
+        st = srv.stats()
+    assert st["completed"] == 6
+    assert st["peak_bytes"] <= budget
+    assert st["peak_active"] <= 2
+    for (Xh, k), (C, L, info), i in zip(probs, res, range(6)):
+        _check_against_oracle(Xh, C, L, info, k, 0.1, i, (10, 10), (1e-4, 1e-4), f"budget {i}")
+
+
+def test_server_rejects_bad_request_and_unknown_ticket():
+    with km.Server() as srv:
+        with pytest.raises(km.KMeansError) as e:
+            srv.submit(torch.zeros((10, 4)), 20, 0.5, 0)
+        assert e.value.status == km.KM_EINVAL
+        res = km.km_result()
+        rc = km.load().km_server_wait(srv._h, 12345, res, 0)
+        assert rc == km.KM_ENOTFOUND
