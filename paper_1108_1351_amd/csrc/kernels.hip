@@ -329,7 +329,30 @@ __global__ void k_stage_reset(PassState* st) {
   st->xn2max_bits = 0u;
   st->qcount = 0u;
   st->ticket = 0u;
+  st->dcn_bits = 0u;
   st->done = 0;
+}
+
+// Rounding error of one BF16 entry of the screen's center copy: the stored
+// value minus -2c, exactly (both fit in FP64).
+__device__ __forceinline__ double bf16_err(uint16_t b, double c) {
+  return (double)__uint_as_float((uint32_t)b << 16) + 2.0 * c;
+}
+
+// Publishes a block's squared rounding-error norm into the running maximum
+// (non-negative floats order as their bits); rounded up so that the stored
+// bound is not below the exact norm.
+__device__ __forceinline__ void dcn_max(PassState* st, double e2) {
+  const float e = (float)(sqrt(e2) * (1.0 + 0x1p-40)) * (1.0f + 0x1p-22f);
+  atomicMax(&st->dcn_bits, __float_as_uint(e));
+}
+
+// The last block of a kernel that rewrote the copy: the maximum becomes the
+// bound the screen reads, and the accumulator starts over.
+__device__ __forceinline__ void dcn_publish(PassState* st) {
+  st->dcn = __uint_as_float(__hip_atomic_load(&st->dcn_bits, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT));
+  st->dcn_bits = 0u;
 }
 
 hipError_t stage_reset(PassState* st, hipStream_t s) {
@@ -1471,6 +1494,29 @@ __device__ __forceinline__ v8bf load8_bf16(const T* __restrict__ row, int t0, in
   return __builtin_bit_cast(v8bf, b);
 }
 
+// As load8_bf16, also adding the squared rounding errors of FP32 data to r2
+// (BF16 data is taken exactly).
+template <typename T>
+__device__ __forceinline__ v8bf load8_bf16(const T* __restrict__ row, int t0, int d, bool valid,
+                                           float& r2) {
+  if constexpr (sizeof(T) == 2) {
+    return load8_bf16<T>(row, t0, d, valid);
+  } else {
+    u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid) {
+      const T* p = row + t0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (t0 + e < d) {
+          b[e] = f32_to_bf16(p[e]);
+          const float r = p[e] - __uint_as_float((uint32_t)b[e] << 16);  // exact
+          r2 = __builtin_fmaf(r, r, r2);
+        }
+    }
+    return __builtin_bit_cast(v8bf, b);
+  }
+}
+
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
@@ -1702,9 +1748,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
   int BG = 5;
   while ((1 << BG) < 32 * nct) ++BG;
   const int GM = (1 << BG) - 1;
-  const float B = st->B, cmax = st->cmax;
-  const float eb = (sizeof(T) == 4 ? 2.f : 1.f) * 0x1p-8f * 1.01f;
-  const float ea = (float)(KD + 8) * 0x1p-24f * 1.01f;
+  const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f;
+  // FP32 accumulation of a score, with any rounding of the partial sums
+  const float ea = (float)(KD + 8) * 0x1p-23f * 1.01f;
   const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
   const int64_t per_block = NW * PT * 32;
   int64_t nfull = 0, ncand = 0;
@@ -1740,17 +1786,17 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
     v8bf x[PT][KS];
     int64_t ip[PT];
     bool valid[PT];
-    float xn[PT];
+    float xn[PT], xr[PT];
     int m1[PT][8], m2[PT][8];  // per slot pair (rows r, r ^ 1): the two smallest keys
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
       const int64_t e = base + (int64_t)(wave * PT + p) * 32 + pc;
       valid[p] = e < n;
       ip[p] = valid[p] ? e : 0;
-      float s2 = 0.f;
+      float s2 = 0.f, r2 = 0.f;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        x[p][s] = load8_bf16<T>(X + ip[p] * d, 16 * s + 8 * h, d, valid[p]);
+        x[p][s] = load8_bf16<T>(X + ip[p] * d, 16 * s + 8 * h, d, valid[p], r2);
         const uint4 w = __builtin_bit_cast(uint4, x[p][s]);
         const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -1760,6 +1806,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
         }
       }
       xn[p] = sqrtf(s2 + __shfl_xor(s2, 32)) * 1.01f;
+      xr[p] = sqrtf(r2 + __shfl_xor(r2, 32)) * 1.01f;
 #pragma unroll
       for (int g = 0; g < 8; ++g) m1[p][g] = m2[p][g] = INT_MAX;
     }
@@ -1816,7 +1863,12 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
     if (base + (int64_t)gridDim.x * per_block < n) issue_stage(rot, cb0, bb0);
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
-      const float E2 = 2.f * (eb * xn[p] * cmax + ea * (cmax * cmax + B + 2.f * xn[p] * cmax));
+      // Two scores differ from their exact values (||c||^2 + B - 2 x.c) by at most
+      // E2 together: x^ . (e_1 - e_2) for the centers' rounding errors e_j
+      // (||e_j|| <= dcn), 2 (x^ - x) . (c_1 - c_2) for rounded FP32 data, and
+      // the FP32 accumulation of both.
+      const float E2 = 2.f * xn[p] * dcn + 4.f * xr[p] * cmax +
+                       2.f * ea * (cmax * cmax + B + 2.f * xn[p] * cmax);
       // tracked keys -> global keys (value bits above BG, center index below)
       int g4[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
       int mm2 = INT_MAX;
@@ -2113,7 +2165,7 @@ __device__ void finalize_center(
   const int64_t C = (int64_t)k * (d + 1);
   long long* col = slots + (int64_t)j * (d + 1);
   __shared__ long long red[256];
-  __shared__ double rd[256], rn[256];
+  __shared__ double rd[256], rn[256], re[256];
   __shared__ int last;
   long long v = 0;
   if (tid < kSlots) {
@@ -2129,7 +2181,7 @@ __device__ void finalize_center(
   const long long Nj = red[0];
   __syncthreads();
   const int F = st->F;
-  double sh = 0.0, nn = 0.0;
+  double sh = 0.0, nn = 0.0, ee = 0.0;
   const int r = tid & 31, c = tid >> 5;  // 32 slots x 8 dims per round
   for (int t0 = 0; t0 < d; t0 += 8) {
     const int t = t0 + c;
@@ -2154,7 +2206,12 @@ __device__ void finalize_center(
         nn += cnew * cnew;
         c64[(int64_t)j * d + t] = cnew;
         cw[(int64_t)j * d + t] = (float)cnew;
-        if (cb16) cb16[(int64_t)j * kd16 + t] = f32_to_bf16((float)(-2.0 * cnew));
+        if (cb16) {
+          const uint16_t b = f32_to_bf16((float)(-2.0 * cnew));
+          cb16[(int64_t)j * kd16 + t] = b;
+          const double e = bf16_err(b, cnew);
+          ee += e * e;
+        }
       }
       if (S_out) S_out[(int64_t)j * d + t] = sum;
     }
@@ -2162,14 +2219,17 @@ __device__ void finalize_center(
   }
   rd[tid] = sh;
   rn[tid] = nn;
+  re[tid] = ee;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if (tid < o) {
       rd[tid] += rd[tid + o];
       rn[tid] += rn[tid + o];
+      re[tid] += re[tid + o];
     }
     __syncthreads();
   }
+  const bool new_copy = update && cb16;  // the BF16 copy of this center was rewritten
   if (tid == 0) {
     if (update) {
       shiftj[j] = sqrt(rd[0]);
@@ -2178,6 +2238,7 @@ __device__ void finalize_center(
       emptyj[j] = Nj == 0 ? 1 : 0;
       if (cnB) cnB[j] = (float)(rn[0] + (double)st->B);
     }
+    if (new_copy) dcn_max(st, re[0]);
     if (N_out) N_out[j] = (int64_t)Nj;
     __threadfence();
     last = atomicAdd(&st->ticket, 1u) == (unsigned)(k - 1) ? 1 : 0;
@@ -2187,7 +2248,10 @@ __device__ void finalize_center(
     __threadfence();
     conclude_block(st, Jpart, upart, nb, jslots, shiftj, cnorm, emptyj, k, update != 0, J_hist,
                    shift_hist, mark_labelled);
-    if (tid == 0) st->ticket = 0u;
+    if (tid == 0) {
+      if (new_copy) dcn_publish(st);
+      st->ticket = 0u;
+    }
   }
   __syncthreads();  // the shared arrays may be reused by a following call
 }
@@ -2333,23 +2397,40 @@ __global__ __launch_bounds__(256) void k_fill_uniform(void* __restrict__ p, int6
   }
 }
 
-// BF16 copy of -2 c (dims padded with zeros to kd16) and ||c||^2 + B.
+// BF16 copy of -2 c (dims padded with zeros to kd16) and ||c||^2 + B; the
+// largest rounding-error norm of a row becomes st->dcn (the last block
+// publishes it).
 __global__ __launch_bounds__(64) void k_prep_bf16(const double* __restrict__ c64, int k, int d,
-                                                  int kd16, const PassState* __restrict__ st,
+                                                  int kd16, PassState* __restrict__ st,
                                                   uint16_t* __restrict__ cb16,
                                                   float* __restrict__ cnB) {
   const int j = blockIdx.x, lane = threadIdx.x;
-  double acc = 0.0;
+  double acc = 0.0, e2 = 0.0;
   for (int t = lane; t < kd16; t += 64) {
     const double c = (t < d && j < k) ? c64[(int64_t)j * d + t] : 0.0;
-    cb16[(int64_t)j * kd16 + t] = f32_to_bf16((float)(-2.0 * c));
+    const uint16_t b = f32_to_bf16((float)(-2.0 * c));
+    cb16[(int64_t)j * kd16 + t] = b;
     acc += c * c;
+    const double e = bf16_err(b, c);
+    e2 += e * e;
   }
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) cnB[j] = j < k ? (float)(acc + (double)st->B) : 1e30f;
+  for (int o = 32; o > 0; o >>= 1) {
+    acc += __shfl_xor(acc, o);
+    e2 += __shfl_xor(e2, o);
+  }
+  if (lane == 0) {
+    cnB[j] = j < k ? (float)(acc + (double)st->B) : 1e30f;
+    dcn_max(st, e2);
+    __threadfence();
+    if (atomicAdd(&st->ticket, 1u) == gridDim.x - 1) {
+      __threadfence();
+      dcn_publish(st);
+      st->ticket = 0u;
+    }
+  }
 }
 
-hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, const PassState* st,
+hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, PassState* st,
                      uint16_t* cb16, float* cnB, hipStream_t s) {
   hipLaunchKernelGGL(k_prep_bf16, dim3((unsigned)bf16_rows(k)), dim3(64), 0, s, c64, k, d, kd16,
                      st, cb16, cnB);

@@ -53,6 +53,11 @@ struct PassState {
   int64_t uncertain;   // labels settled by the FP64 check over all centers, cumulative
   int64_t pairs;       // labels settled by FP64 between the best two candidates, cumulative
   int64_t rows;
+  // BF16 screen: dcn >= max_j ||bf16(-2 c_j) + 2 c_j|| for the current centers
+  // (the exact rounding error of the screen's center copy); dcn_bits gathers
+  // the maximum over the blocks of the kernel that writes the copy.
+  float dcn;
+  uint32_t dcn_bits;
 };
 
 // One instance of a batched pass: many independent k-means problems advance
@@ -104,7 +109,7 @@ hipError_t stage_reset(PassState* st, hipStream_t s);
 hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, bool norms,
                      PassState* st, hipStream_t s);
 hipError_t zero_i64(long long* p, int64_t count, hipStream_t s);
-hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, const PassState* st,
+hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, PassState* st,
                      uint16_t* cb16, float* cnB, hipStream_t s);
 hipError_t prep_centers(const double* c64, int32_t k, int32_t d, float* cw, float* cn,
                         double* cnorm, hipStream_t s);

@@ -278,7 +278,7 @@ def test_near_duplicate_centers_resolved_in_fp64(d, k):
                                        (64, 300, "f32"), (256, 50, "bf16"), (16, 64, "f32"),
                                        (200, 129, "f32")])
 def test_bf16_screen_step_parity(d, k, dtype):
-    """BF16 MFMA screen, top-4 keys, certified FP32 re-rank and FP64 decisions."""
+    """BF16 MFMA screen, certified candidates, FP32 re-rank and FP64 decisions."""
     n = 12_289
     print(f"[bf16 step] n={n} d={d} k={k} {dtype}", flush=True)
     Xh = _mixture(n, d, min(k, 60), seed=d + 3 * k, dtype=dtype)
@@ -313,6 +313,53 @@ def test_bf16_screen_crowded_centers(copies):
     ex = exempt_mask(Xh, C)
     assert np.array_equal(out["labels"].cpu().numpy()[~ex], ref.labels[~ex])
     assert abs(out["J"] - ref.J) <= 1e-9 * ref.J
+
+
+def _far_centers(d, count, seed):
+    rng = np.random.default_rng(seed)
+    return 40.0 + rng.normal(0, 3.0, size=(count, d))
+
+
+@pytest.mark.parametrize("extra", [0, 38])
+@pytest.mark.parametrize("m", [0, 5, 40, 100])
+def test_bf16_screen_band_covers_center_rounding(m, extra):
+    """Adversarial BF16 rounding of the centers.  x = (1, ..., 1); c1 and c2 are
+    constant vectors just below and just above a BF16 rounding midpoint of -2c,
+    so every entry of the screen's copy of c1 rounds up by almost half an ulp
+    and every entry of c2's rounds down.  c1 is the nearer center, but the
+    screen's scores put c2 ahead by nearly 128 * 2^-6 = 2, more than half of
+    the worst-case error of two scores: only a band that covers the full
+    rounding of both centers sends the point to the re-rank."""
+    d = 128
+    v1, v2 = 1 + (m + 0.49) * 2.0 ** -7, 1 + (m + 0.51) * 2.0 ** -7
+    C = np.vstack([np.full((1, d), v1), np.full((1, d), v2), _far_centers(d, extra, m)])
+    Xh = synth_bf16(np.ones((64, d)))
+    ref = oracle.step(Xh, C)
+    assert (ref.labels == 0).all()
+    print(f"[bf16 band] m={m} k={len(C)}", flush=True)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="bf16_rerank")
+    assert (lab.cpu().numpy() == 0).all()
+    assert abs(J - ref.J) <= 1e-9 * ref.J
+
+
+@pytest.mark.parametrize("extra", [0, 38])
+def test_bf16_screen_band_covers_fp32_data_rounding(extra):
+    """FP32 data whose BF16 roundings all point one way: with c1 = -c2 = 0.5
+    (exact in BF16), the rounded point prefers c1 by 0.78 while c2 is nearer;
+    the band term 4 ||x^ - x|| max||c|| (about 1.0 here) catches it."""
+    d = 128
+    x = np.empty(d, np.float32)
+    x[0::2] = np.float32(1 + 0.51 * 2.0 ** -7)
+    x[1::2] = np.float32(-(1 + 0.49 * 2.0 ** -7))
+    x[1] = np.float32(-1.109375)
+    Xh = np.tile(x, (64, 1))
+    C = np.vstack([np.full((1, d), 0.5), np.full((1, d), -0.5), _far_centers(d, extra, 3)])
+    ref = oracle.step(Xh, C)
+    assert (ref.labels == 1).all()
+    print(f"[bf16 band f32] k={len(C)}", flush=True)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="bf16_rerank")
+    assert (lab.cpu().numpy() == 1).all()
+    assert abs(J - ref.J) <= 1e-9 * ref.J
 
 
 def synth_bf16(A):
