@@ -1702,6 +1702,10 @@ __device__ __forceinline__ int opaque_vgpr(int v) {
   return r;
 }
 
+// Marks v as used here (no instruction): keeps the code that computes it from
+// being sunk past this point by the optimizer.
+__device__ __forceinline__ void pin_here(int& v) { asm volatile("" : "+v"(v)); }
+
 // The BF16 screen of all points.  A block (4 waves) takes 4*PT tiles of 32
 // points; each wave keeps its rows as the B operand of 32x32x16 BF16 MFMAs in
 // registers.  Centers stream through LDS in stages of 128 rows, double-buffered:
@@ -1727,16 +1731,17 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
   if (gated(gate)) return;
   constexpr int KD = KS * 16;
   constexpr int C8 = KD / 8;                  // 16-byte chunks per center row
-  constexpr int SW = C8 < 16 ? C8 - 1 : 15;   // chunk swizzle mask (spreads rows over banks)
   constexpr int SC = 128;                     // center rows per stage
-  constexpr int RPI = 1024 / (KD * 2);        // rows per 1 KB LDS-direct load
-  constexpr int NI = SC / RPI;                // such loads per stage
+  constexpr int NI = SC * KD * 2 / 1024;      // 1 KB LDS-direct loads per stage
   // two stage buffers as separate objects, each used by its own code path, so
   // that reads of one need not wait for the LDS-direct loads into the other
   __shared__ __align__(16) uint16_t cb0[SC * KD], cb1[SC * KD];
   __shared__ __align__(16) float bb0[SC], bb1[SC];
   __shared__ int cand_j[64 * NW * 4];
-  const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31;
+  // wave-uniform (scalar) wave index: the stage-copy loops below then run on
+  // the scalar unit
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // an even number of stages over the padded rows (padding rows score 1e30):
   // the stage loop below runs in pairs without a branch
   const int nst = ((k + 2 * SC - 1) / (2 * SC)) * 2, nct = nst * (SC / 32);
@@ -1754,15 +1759,18 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
   const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
   const int64_t per_block = NW * PT * 32;
   int64_t nfull = 0, ncand = 0;
-  // Stage g of the (padded) center rows into buffer b with LDS-direct loads:
-  // lane L of load i fills 16 bytes at row i*RPI + L/C8, position L%C8, which
-  // holds chunk (L%C8) ^ (row & SW) of that row.
+  // Stage g of the (padded, tiled) center copy into a buffer with LDS-direct
+  // loads: the stage is one contiguous range, copied as is.  In LDS, chunk c of
+  // row r of tile t sits at ((t * C8 + c) * 32 + r) * 16 bytes, so the 32 rows
+  // a wave reads for one MFMA operand are 512 contiguous bytes (no bank conflicts).
   auto issue_stage = [&](int g, uint16_t* cdst, float* bdst) {
-    for (int i = wave; i < NI; i += NW) {
-      const int row = i * RPI + lane / C8, c = (lane % C8) ^ (row & SW);
+    static_assert(NI % NW == 0, "every wave copies the same number of 1 KB pieces");
+#pragma unroll
+    for (int u = 0; u < NI / NW; ++u) {
+      const int i = u * NW + wave;
       __builtin_amdgcn_global_load_lds(
-          static_cast<const void*>(cb16 + ((int64_t)g * SC + row) * KD + c * 8),
-          static_cast<void*>(cdst + i * RPI * KD), 16, 0, 0);
+          static_cast<const void*>(cb16 + (int64_t)g * SC * KD + i * 512 + lane * 8),
+          static_cast<void*>(cdst + i * 512), 16, 0, 0);
     }
     static_assert(SC % 64 == 0, "a stage's biases are whole 64-float loads");
     for (int i = NW - 1 - wave; i < SC / 64; i += NW)
@@ -1810,40 +1818,86 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
 #pragma unroll
       for (int g = 0; g < 8; ++g) m1[p][g] = m2[p][g] = INT_MAX;
     }
-    // the 32-center tiles of stage gs, read from one buffer
-    auto compute_stage = [&](int gs, const uint16_t* cbuf, const float* bbuf) {
-#pragma unroll 1
-      for (int t = 0; t < SC / 32; ++t) {
-        const int ct = gs * (SC / 32) + t;
-        {
-          v16f bias;
+    // Software pipeline over the 32-center tiles: while the MFMAs of tile t
+    // accumulate into one set of registers, the key updates of tile t-1 read
+    // the other set, and the LDS reads of later steps are in flight (a ring of
+    // four A operands two steps ahead, and the next tile's bias).  accP holds
+    // the pending tile (index ctP); at the start of a batch it holds scores of
+    // 1e30, which never displace a real key (see the merge below).
+    v16f accA[PT], accP[PT];
+    int ctP = 0;
 #pragma unroll
-          for (int r = 0; r < 16; ++r) bias[r] = bbuf[t * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
-          const int row = t * 32 + pc;
-          v8bf a[KS];
+    for (int p = 0; p < PT; ++p)
 #pragma unroll
-          for (int s = 0; s < KS; ++s)
-            a[s] = *reinterpret_cast<const v8bf*>(&cbuf[row * KD + (((2 * s + h) ^ (row & SW)) * 8)]);
-          v16f acc[PT];
+      for (int r = 0; r < 16; ++r) accP[p][r] = 1e30f;
+    // key update of score (p, r) of a tile: three VALU operations
+    auto key1 = [&](const v16f (&acc)[PT], int p, int r, int vc0, int vc1) {
+      const int kv = (__float_as_int(acc[p][r]) & ~TM) | ((r & 1) ? vc1 : vc0);
+      m2[p][r >> 1] = med3_i32(m1[p][r >> 1], kv, m2[p][r >> 1]);
+      m1[p][r >> 1] = min(m1[p][r >> 1], kv);
+    };
+    auto keys = [&](const v16f (&acc)[PT], int ct) {
+      const int vc0 = opaque_vgpr(ct << 1), vc1 = opaque_vgpr((ct << 1) | 1);
 #pragma unroll
-          for (int p = 0; p < PT; ++p)
-            acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], x[p][0], bias, 0, 0, 0);
+      for (int p = 0; p < PT; ++p)
 #pragma unroll
-          for (int s = 1; s < KS; ++s)
+        for (int r = 0; r < 16; ++r) key1(acc, p, r, vc0, vc1);
+    };
+    constexpr int NT = SC / 32;          // tiles per stage
+    constexpr int NSTEP = NT * KS;       // MFMA steps (of PT MFMAs) per stage
+    constexpr int SPG = 16 / KS;         // key updates placed after each MFMA
+    static_assert(16 % KS == 0, "key updates split evenly over the MFMAs");
+    // the A operand of step i (tile i / KS, dims 16 (i % KS) ...) of a stage buffer
+    auto lds_a = [&](const uint16_t* cbuf, int i) -> v8bf {
+      const int t = i / KS, s = i % KS;
+      return *reinterpret_cast<const v8bf*>(&cbuf[((t * C8 + 2 * s + h) * 32 + pc) * 8]);
+    };
+    auto lds_bias = [&](const float* bbuf, int t, v16f& b) {
 #pragma unroll
-            for (int p = 0; p < PT; ++p)
-              acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], x[p][s], acc[p], 0, 0, 0);
-          const int vc0 = opaque_vgpr(ct << 1), vc1 = opaque_vgpr((ct << 1) | 1);
+      for (int r = 0; r < 16; ++r) b[r] = bbuf[t * 32 + 8 * (r >> 2) + 4 * h + (r & 3)];
+    };
+    // One tile: each MFMA into `out` is followed by its share of the key
+    // updates of `in` (tile ctin) and fenced, so that the scheduler keeps the
+    // interleave (the matrix cores and the VALU then work side by side).
+    auto tile = [&](int t, const uint16_t* cbuf, const float* bbuf, v8bf (&ring)[4], v16f& bias,
+                    v16f (&out)[PT], const v16f (&in)[PT], int ctin) {
+      const int vc0 = opaque_vgpr(ctin << 1), vc1 = opaque_vgpr((ctin << 1) | 1);
 #pragma unroll
-          for (int p = 0; p < PT; ++p)
+      for (int s = 0; s < KS; ++s) {
+        const int i = t * KS + s;
+        if (i + 2 < NSTEP) ring[(i + 2) & 3] = lds_a(cbuf, i + 2);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int kv = (__float_as_int(acc[p][r]) & ~TM) | ((r & 1) ? vc1 : vc0);
-              m2[p][r >> 1] = med3_i32(m1[p][r >> 1], kv, m2[p][r >> 1]);
-              m1[p][r >> 1] = min(m1[p][r >> 1], kv);
+        for (int p = 0; p < PT; ++p) {
+          out[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ring[i & 3], x[p][s],
+                                                           s == 0 ? bias : out[p], 0, 0, 0);
+          const int q0 = (s * PT + p) * SPG;
+#pragma unroll
+          for (int q = q0; q < q0 + SPG; ++q) {
+            key1(in, q >> 4, q & 15, vc0, vc1);
+            if (q & 1) {
+              pin_here(m1[q >> 4][(q & 15) >> 1]);
+              pin_here(m2[q >> 4][(q & 15) >> 1]);
             }
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
+        if (s == 0 && t + 1 < NT) lds_bias(bbuf, t + 1, bias);
       }
+    };
+    // the four tiles of stage gs, read from one buffer; tile 3 stays pending
+    auto compute_stage = [&](int gs, const uint16_t* cbuf, const float* bbuf) {
+      static_assert(NT == 4, "the stage code below names four tiles");
+      v8bf ring[4];
+      v16f bias;
+      lds_bias(bbuf, 0, bias);
+      ring[0] = lds_a(cbuf, 0);
+      ring[1] = lds_a(cbuf, 1);
+      const int ct0 = gs * NT;
+      tile(0, cbuf, bbuf, ring, bias, accA, accP, ctP);
+      tile(1, cbuf, bbuf, ring, bias, accP, accA, ct0);
+      tile(2, cbuf, bbuf, ring, bias, accA, accP, ct0 + 1);
+      tile(3, cbuf, bbuf, ring, bias, accP, accA, ct0 + 2);
+      ctP = ct0 + 3;
     };
     stage_sync();
     // stages in pairs: buffer 0 holds stages 0, 2, ..., buffer 1 stages 1, 3, ...;
@@ -1859,6 +1913,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
       stage_sync();
       gs = gs2;
     }
+    keys(accP, ctP);
     // both buffers are free: the next tile's first stage loads during the re-rank
     if (base + (int64_t)gridDim.x * per_block < n) issue_stage(rot, cb0, bb0);
 #pragma unroll
@@ -2007,7 +2062,7 @@ __global__ __launch_bounds__(512) void k_rescreen_bf16(
         const int row = e / (KD / 8), c8 = e - row * (KD / 8);
         const int j = ct * 32 + row;
         uint4 v = {0u, 0u, 0u, 0u};
-        if (j < k) v = *reinterpret_cast<const uint4*>(cb16 + (int64_t)j * KD + c8 * 8);
+        if (j < k) v = *reinterpret_cast<const uint4*>(cb16 + cb16_at(j, c8 * 8, KD));
         *reinterpret_cast<uint4*>(&ctile[row * RS + c8 * 8]) = v;
       }
       if (threadIdx.x < 32) {
@@ -2208,7 +2263,7 @@ __device__ void finalize_center(
         cw[(int64_t)j * d + t] = (float)cnew;
         if (cb16) {
           const uint16_t b = f32_to_bf16((float)(-2.0 * cnew));
-          cb16[(int64_t)j * kd16 + t] = b;
+          cb16[cb16_at(j, t, kd16)] = b;
           const double e = bf16_err(b, cnew);
           ee += e * e;
         }
@@ -2409,7 +2464,7 @@ __global__ __launch_bounds__(64) void k_prep_bf16(const double* __restrict__ c64
   for (int t = lane; t < kd16; t += 64) {
     const double c = (t < d && j < k) ? c64[(int64_t)j * d + t] : 0.0;
     const uint16_t b = f32_to_bf16((float)(-2.0 * c));
-    cb16[(int64_t)j * kd16 + t] = b;
+    cb16[cb16_at(j, t, kd16)] = b;
     acc += c * c;
     const double e = bf16_err(b, c);
     e2 += e * e;

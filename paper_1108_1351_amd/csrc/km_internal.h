@@ -19,6 +19,14 @@ constexpr int kScreenRows = 256;       // BF16 center rows are padded to a multi
 inline int64_t bf16_rows(int32_t k) {
   return ((int64_t)k + kScreenRows - 1) / kScreenRows * kScreenRows;
 }
+// Position of entry (row j, dim t) in the BF16 screen's center copy (kd16 dims
+// per row).  The copy is tiled: tiles of 32 rows; in a tile, the 16-byte chunks
+// (8 dims) of all 32 rows for chunk 0, then chunk 1, and so on.  A stage of
+// tiles is then one contiguous range, and the rows of one chunk are contiguous
+// for the MFMA operand reads.
+__host__ __device__ inline int64_t cb16_at(int64_t j, int t, int kd16) {
+  return (((j >> 5) * (kd16 >> 3) + (t >> 3)) * 32 + (j & 31)) * 8 + (t & 7);
+}
 
 // Progress of one radix selection of the r smallest 64-bit keys.  When done,
 // a key is selected iff its top `bits` bits are <= prefix (keys are distinct).
@@ -126,7 +134,7 @@ struct PassBufs {
   long long* scnt;     // [k * sort_chunks] label counts per chunk, then their offsets
   long long* stot;     // [scan tiles + 1] tile totals of the offset scan
   long long* rstart;   // [k + 1] first position of every label's run
-  uint16_t* cb16;      // [bf16_rows(k)][ks*16] BF16 (-2 c) of the BF16 screen, zero padded
+  uint16_t* cb16;      // bf16_rows(k) x ks*16 BF16 (-2 c) of the BF16 screen, tiled (cb16_at)
   float* cnB;          // [bf16_rows(k)] ||c||^2 + B of the BF16 screen (1e30 on padding rows)
   int32_t* queue;      // [n] points of the BF16 screen with more than 4 candidates
   float* qthr;         // [n] their score thresholds
