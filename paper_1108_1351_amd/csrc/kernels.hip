@@ -1702,6 +1702,13 @@ __device__ __forceinline__ int opaque_vgpr(int v) {
   return r;
 }
 
+// The value x of the lane in the other half of the wave (lane ^ 32): one
+// permlane32 swap, no LDS traffic.  h is the lane's half (lane >> 5).
+__device__ __forceinline__ int other_half(int x, int h) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return h ? (int)r[0] : (int)r[1];
+}
+
 // Marks v as used here (no instruction): keeps the code that computes it from
 // being sunk past this point by the optimizer.
 __device__ __forceinline__ void pin_here(int& v) { asm volatile("" : "+v"(v)); }
@@ -1738,6 +1745,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
   __shared__ __align__(16) uint16_t cb0[SC * KD], cb1[SC * KD];
   __shared__ __align__(16) float bb0[SC], bb1[SC];
   __shared__ int cand_j[64 * NW * 4];
+  __shared__ float pf_sink[64];  // lands the L2 prefetch touches below (never read)
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31;
   // wave-uniform (scalar) wave index: the stage-copy loops below then run on
   // the scalar unit
@@ -1777,6 +1785,25 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
       __builtin_amdgcn_global_load_lds(
           static_cast<const void*>(cnB + (int64_t)g * SC + 64 * i + lane),
           static_cast<void*>(bdst + 64 * i), 4, 0, 0);
+  };
+  // The first 16 KB of the rows this wave takes in the batch starting at
+  // `nbase`, brought into L2 ahead of their loads: one 4-byte LDS-direct copy
+  // per 128-byte line (the data lands in pf_sink and is never read).  The
+  // copies complete by the next stage barrier.
+  const int64_t xbytes = n * (int64_t)d * (int64_t)sizeof(T);
+  const bool x_aligned = (reinterpret_cast<uintptr_t>(X) & 3u) == 0;
+  auto prefetch_rows = [&](int64_t nbase) {
+    if (nbase >= n || !x_aligned) return;
+    const int64_t b0 = (nbase + (int64_t)wave * PT * 32) * (int64_t)d * (int64_t)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      // a 4-byte aligned word that lies inside X
+      const int64_t off = (b0 + ((int64_t)i * 64 + lane) * 128) & ~(int64_t)3;
+      const int64_t at = off + 4 <= xbytes ? off : 0;
+      __builtin_amdgcn_global_load_lds(
+          static_cast<const void*>(reinterpret_cast<const char*>(X) + at),
+          static_cast<void*>(pf_sink), 4, 0, 0);
+    }
   };
   // every wave's LDS-direct loads are in LDS before the barrier
   auto stage_sync = [&]() {
@@ -1909,6 +1936,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
       compute_stage(gs, cb0, bb0);
       stage_sync();
       if (g + 2 < nst) issue_stage(gs2, cb0, bb0);
+      else prefetch_rows(base + (int64_t)gridDim.x * per_block);
       compute_stage(gs1, cb1, bb1);
       stage_sync();
       gs = gs2;
@@ -1924,42 +1952,67 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
       // the FP32 accumulation of both.
       const float E2 = 2.f * xn[p] * dcn + 4.f * xr[p] * cmax +
                        2.f * ea * (cmax * cmax + B + 2.f * xn[p] * cmax);
-      // tracked keys -> global keys (value bits above BG, center index below)
-      int g4[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-      int mm2 = INT_MAX;
-      auto insert = [&](int kv) {
-        g4[3] = med3_i32(g4[2], kv, g4[3]);
-        g4[2] = med3_i32(g4[1], kv, g4[2]);
-        g4[1] = med3_i32(g4[0], kv, g4[1]);
-        g4[0] = min(g4[0], kv);
+      // Tracked keys -> global keys (score bits above BG, center index below).
+      // After the first tile every slot pair holds two keys (real ones, or the
+      // 1e30 keys of the batch start), so none is empty.  Within a pair the
+      // global keys keep the order of their score bits, which is all that the
+      // merge below needs: keys whose score bits agree are within the error
+      // band of each other, so the choice between them is made exactly later.
+      const int hoff = 4 * h;
+      auto glob = [&](int a, int c) {  // c: offset of the pair's even row
+        const int u = ((a & (TM - 1)) << 4) + hoff + c;  // 32 ct + row offset
+        return (a & ~GM) | u | (a & 1);
       };
+      // two sorted pairs -> sorted four
+      auto merge22 = [](int a0, int a1, int b0, int b1, int (&o)[4]) {
+        const int x = max(a0, b0), y = min(a1, b1);
+        o[0] = min(a0, b0);
+        o[1] = min(x, y);
+        o[2] = max(x, y);
+        o[3] = max(a1, b1);
+      };
+      // two sorted fours -> the sorted four smallest (bitonic merge)
+      auto merge44 = [](const int (&a)[4], const int (&b)[4], int (&o)[4]) {
+        const int c0 = min(a[0], b[3]), c1 = min(a[1], b[2]), c2 = min(a[2], b[1]),
+                  c3 = min(a[3], b[0]);
+        const int d0 = min(c0, c2), d2 = max(c0, c2), d1 = min(c1, c3), d3 = max(c1, c3);
+        o[0] = min(d0, d1);
+        o[1] = max(d0, d1);
+        o[2] = min(d2, d3);
+        o[3] = max(d2, d3);
+      };
+      int q4[4][4], r4[2][4], g4[4];
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        // rows 2g, 2g+1 of the lane: center offset 8(g/2) + 4h + 2(g%2) + parity
-        const int off = 8 * (g >> 1) + 4 * h + 2 * (g & 1);
-        auto glob = [&](int a) {
-          return a == INT_MAX ? INT_MAX
-                              : ((a & ~GM) | (32 * ((a & TM) >> 1) + off + (a & 1)));
-        };
-        const int ga = glob(m1[p][g]), gb = glob(m2[p][g]);
-        insert(ga);
-        insert(gb);
-        mm2 = min(mm2, gb);
+      for (int u = 0; u < 4; ++u) {
+        // slot pairs 2u and 2u+1: rows at offsets 8u + 4h + {0,1} and {2,3}
+        merge22(glob(m1[p][2 * u], 8 * u), glob(m2[p][2 * u], 8 * u),
+                glob(m1[p][2 * u + 1], 8 * u + 2), glob(m2[p][2 * u + 1], 8 * u + 2), q4[u]);
       }
-      int o[4];
+      merge44(q4[0], q4[1], r4[0]);
+      merge44(q4[2], q4[3], r4[1]);
+      merge44(r4[0], r4[1], g4);
+      // the other lane half's four
+      {
+        int o[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) o[u] = __shfl_xor(g4[u], 32);
+        for (int u = 0; u < 4; ++u) o[u] = other_half(g4[u], h);
+        int t[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) insert(o[u]);
-      mm2 = min(mm2, __shfl_xor(mm2, 32));
+        for (int u = 0; u < 4; ++u) t[u] = g4[u];
+        merge44(t, o, g4);
+      }
+      int mm2 = m2[p][0];
+#pragma unroll
+      for (int g = 1; g < 8; ++g) mm2 = min(mm2, m2[p][g]);
+      mm2 = min(mm2, other_half(mm2, h));
       float v[4];
       int jj[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        v[u] = g4[u] == INT_MAX ? INFINITY : __int_as_float(g4[u] & ~GM);
-        jj[u] = g4[u] == INT_MAX ? INT_MAX : (g4[u] & GM);
+        v[u] = __int_as_float(g4[u] & ~GM);
+        jj[u] = g4[u] & GM;
       }
-      const float vm2 = mm2 == INT_MAX ? INFINITY : __int_as_float(mm2 & ~GM);
+      const float vm2 = __int_as_float(mm2 & ~GM);
       auto apart = [&](float a, float b) {
         return (b - a) > E2 + delta * (fabsf(a) + fabsf(b));
       };
@@ -1996,8 +2049,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
         decided = true;
         nc = 0;
       }
-      int ncmax = nc;
-      for (int o2 = 32; o2 > 0; o2 >>= 1) ncmax = max(ncmax, __shfl_xor(ncmax, o2));
+      // the most candidates of a lane in the wave (at most 4)
+      const int ncmax = __ballot(nc >= 4) ? 4 : __ballot(nc >= 3) ? 3 : __ballot(nc >= 2) ? 2
+                      : __ballot(nc >= 1) ? 1 : 0;
       const bool rr = !decided && !full && nc > 0;
       if (ncmax > 0) {
         const int lab =
