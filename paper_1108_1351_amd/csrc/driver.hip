@@ -51,6 +51,7 @@ int64_t blocks_max(const Sizes& z) {
 }
 
 bool any_bf16(const Sizes& z) { return (z.stage1 && z.p1.bf16) || z.p2.bf16; }
+bool any_copy16(const Sizes& z) { return (z.stage1 && copy16(z.p1)) || copy16(z.p2); }
 int ks_max(const Sizes& z) { return std::max(z.stage1 ? z.p1.ks : 0, z.p2.ks); }
 
 // Buffers of the sorted update (split paths), sized for the larger stage.
@@ -96,7 +97,7 @@ Layout make_layout(const Sizes& z) {
   const size_t C = (size_t)z.k * (z.d + 1);
   L.slots = c.take<long long>((size_t)kSlots * C);
   L.jslots = c.take<long long>((size_t)kSlots * 2);
-  L.cb16 = c.take<uint16_t>(any_bf16(z) ? (size_t)bf16_rows(z.k) * 16 * ks_max(z) : 0);
+  L.cb16 = c.take<uint16_t>(any_copy16(z) ? (size_t)bf16_rows(z.k) * 16 * ks_max(z) : 0);
   L.cnb = c.take<float>((size_t)bf16_rows(z.k));
   L.queue = c.take<int32_t>(any_bf16(z) ? (size_t)z.n : 0);
   L.qthr = c.take<float>(any_bf16(z) ? (size_t)z.n : 0);
@@ -164,9 +165,9 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
   if (prof)
     for (int32_t i = 0; i < 3 * max_iter; ++i) ev.push_back(take_event());
   HIP_TRY(stage_reset(b.st, s));
-  HIP_TRY(row_stats(b.X, b.dtype, rows, b.d, !plan.fused, b.st, s));
+  HIP_TRY(row_stats(b.X, b.dtype, rows, b.d, wants_norms(plan), b.st, s));
   HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, b.d, plan.fused ? 0 : plan.pg, s));
-  if (plan.bf16) HIP_TRY(prep_bf16(b.c64, b.k, b.d, plan.ks * 16, b.st, b.cb16, b.cnB, s));
+  if (copy16(plan)) HIP_TRY(prep_bf16(b.c64, b.k, b.d, plan.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * b.k * (b.d + 1), s));
   HIP_TRY(zero_i64(b.jslots, (int64_t)kSlots * 2, s));
   while (launched < max_iter) {
@@ -522,7 +523,7 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
                o_sh = c.take<double>(k), o_em = c.take<int32_t>(k),
                o_st = c.take<PassState>(1), o_slots = c.take<long long>((size_t)kSlots * C_),
                o_qs = c.take<long long>((size_t)kSlots * 2),
-               o_cb = c.take<uint16_t>(p.bf16 ? (size_t)bf16_rows(k) * 16 * p.ks : 0),
+               o_cb = c.take<uint16_t>(copy16(p) ? (size_t)bf16_rows(k) * 16 * p.ks : 0),
                o_cnb = c.take<float>((size_t)bf16_rows(k)), o_q = c.take<int32_t>(p.bf16 ? (size_t)n : 0),
                o_qt = c.take<float>(p.bf16 ? (size_t)n : 0),
                o_jp = c.take<double>((size_t)p.blocks * 2),
@@ -567,9 +568,9 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   HIP_TRY(hipMemcpyAsync(b.c64, C, sizeof(double) * k * d, hipMemcpyDeviceToDevice, s));
   HIP_TRY(prep_centers(b.c64, k, d, b.cw, b.cn, b.cnorm, s));
   HIP_TRY(stage_reset(b.st, s));
-  HIP_TRY(row_stats(X, b.dtype, n, d, !p.fused, b.st, s));
+  HIP_TRY(row_stats(X, b.dtype, n, d, wants_norms(p), b.st, s));
   HIP_TRY(stage_begin(b.st, 1, 0.0, n, b.cnorm, k, d, p.fused ? 0 : p.pg, s));
-  if (p.bf16) HIP_TRY(prep_bf16(b.c64, k, d, p.ks * 16, b.st, b.cb16, b.cnB, s));
+  if (copy16(p)) HIP_TRY(prep_bf16(b.c64, k, d, p.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * k * (d + 1), s));
   HIP_TRY(zero_i64(b.jslots, (int64_t)kSlots * 2, s));
   HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));

@@ -1231,13 +1231,16 @@ __device__ __forceinline__ void load_half(const T* __restrict__ row, int d, int 
 
 // FP64 check of the uncertain points of a 32-point MFMA tile.  Every lane of
 // the wave calls this; point p's row sits in registers x of lanes p (dims
-// [0, H)) and p + 32 (dims [H, 2H)), the FP64 centers in LDS (row stride d+1).
+// [0, H)) and p + 32 (dims [H, 2H)), the FP64 centers in LDS (row stride d+1,
+// or `stride`).
 // Each lane takes centers lane, lane + 64, ...; the wave then reduces (D, j)
 // to the smallest D, lowest j on ties.  The squared distance is the plain
 // direct form summed over t = 0..d-1.
 template <int H>
 __device__ __forceinline__ int64_t mfma_fp64_check(bool unc, const float (&x)[H], int d, int k,
-                                                   const double* __restrict__ cs, int& label) {
+                                                   const double* __restrict__ cs, int& label,
+                                                   int stride = -1) {
+  if (stride < 0) stride = d + 1;
   const int lane = threadIdx.x & 63;
   unsigned long long m = __ballot(unc);
   const int64_t cnt = __popcll(m);
@@ -1253,7 +1256,7 @@ __device__ __forceinline__ int64_t mfma_fp64_check(bool unc, const float (&x)[H]
     double bD = INFINITY;
     int bj = INT_MAX;
     for (int j = lane; j < k; j += 64) {
-      const double* cj = cs + (int64_t)j * (d + 1);
+      const double* cj = cs + (int64_t)j * stride;
       double D = 0.0;
 #pragma unroll
       for (int t = 0; t < 2 * H; ++t) {
@@ -1712,6 +1715,260 @@ __device__ __forceinline__ int other_half(int x, int h) {
 // Marks v as used here (no instruction): keeps the code that computes it from
 // being sunk past this point by the optimizer.
 __device__ __forceinline__ void pin_here(int& v) { asm volatile("" : "+v"(v)); }
+
+// Fused pass for d <= 16 and k <= 128 on the BF16 matrix cores.  A wave takes
+// 32 points at a time; lane half h holds dims [hH, hH + H) of its point (H = KD/2)
+// as K elements 8h .. 8h + H - 1 of the MFMA operands (the others are zero).  For
+// each tile of 32 centers one 32x32x16 BF16 MFMA gives every lane 16 screened
+// scores ||c||^2 + B + x^.c^ of its point (c^ the BF16 copy of -2c, x^ the point
+// as BF16; lane and lane^32 hold the two halves of the tile's centers; the C
+// input is ||c||^2 + B).  Each lane keeps its best three as integer keys; the two
+// halves' keys give the best three of all.  The screen's error band (the bound of
+// the split screen: the exact rounding-error norms of the center copy and of the
+// point, and the FP32 accumulation) certifies the best center; when only the
+// second best is within the band, FP64 distances decide between the two;
+// otherwise the FP64 check over all centers decides.  J in FP64 (each lane half
+// adds its dims' part) and the exact cluster sums as in the FP32 fused pass.
+// FULL: d == KD (no padded dims).
+template <typename T, int KD, int NT, bool FULL>
+__global__ __launch_bounds__(256, 3) void k_fused_screen(
+    const T* __restrict__ X, int64_t n, int d, int k, const uint16_t* __restrict__ cb16,
+    const float* __restrict__ cnB, const double* __restrict__ c64,
+    const PassState* __restrict__ st, const int32_t* __restrict__ gate, int update,
+    long long* __restrict__ slots, double* __restrict__ Jpart, long long* __restrict__ upart,
+    int32_t* __restrict__ labels) {
+  if (gated(gate)) return;
+  constexpr int H = KD / 2;                             // dims per lane half
+  static_assert(KD >= 2 && KD <= 16, "one 16-element K step holds both halves");
+  constexpr int BL = NT == 1 ? 4 : (NT == 2 ? 5 : 6);  // bits of a lane-local index (16*NT values)
+  constexpr int BG = BL + 1;                            // bits of a center index (32*NT centers)
+  constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* cs = reinterpret_cast<double*>(smem);  // [k][KD] FP64 centers, zero past d
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * KD);  // [k][d+1]
+  const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < k * KD; e += 256) {
+    const int j = e / KD, t = e - j * KD;
+    cs[e] = t < d ? c64[(int64_t)j * d + t] : 0.0;
+  }
+  if (update)
+    for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
+  // A operand (center rows 32t + pc, dims hH .. hH + H - 1 of the BF16 copy) and
+  // the C input (rows 8(r/4) + 4h + r%4 of the tile) of every center tile
+  v8bf a[NT];
+  v16f bias[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if constexpr (H == 8) {
+      a[t] = *reinterpret_cast<const v8bf*>(cb16 + cb16_at(32 * t + pc, 8 * h, 16));
+    } else {
+      u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < H; ++e) v[e] = cb16[cb16_at(32 * t + pc, h * H + e, 16)];
+      a[t] = __builtin_bit_cast(v8bf, v);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) bias[t][r] = cnB[32 * t + 8 * (r >> 2) + 4 * h + (r & 3)];
+  }
+  __syncthreads();
+  const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f, scale = st->scale;
+  const float ea = (float)(16 + 8) * 0x1p-23f * 1.01f;
+  const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
+  // FULL: the half row is one aligned vector load (the launcher checks the
+  // alignment of X); otherwise element loads with bounds
+  auto load_x = [&](int64_t row, float (&xo)[H]) {
+    if constexpr (FULL) {
+      const T* p = X + row * KD + h * H;
+      if constexpr (sizeof(T) == 4) {
+        if constexpr (H == 1) {
+          xo[0] = p[0];
+        } else if constexpr (H == 2) {
+          const float2 v = *reinterpret_cast<const float2*>(p);
+          xo[0] = v.x; xo[1] = v.y;
+        } else {
+#pragma unroll
+          for (int q = 0; q < H; q += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(p + q);
+            xo[q] = v.x; xo[q + 1] = v.y; xo[q + 2] = v.z; xo[q + 3] = v.w;
+          }
+        }
+      } else {
+        if constexpr (H == 1) {
+          xo[0] = widen<T>(p[0]);
+        } else if constexpr (H == 2) {
+          const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+          xo[0] = bf16_lo(w); xo[1] = bf16_hi(w);
+        } else if constexpr (H == 4) {
+          const uint2 w = *reinterpret_cast<const uint2*>(p);
+          xo[0] = bf16_lo(w.x); xo[1] = bf16_hi(w.x); xo[2] = bf16_lo(w.y); xo[3] = bf16_hi(w.y);
+        } else {
+          const uint4 w = *reinterpret_cast<const uint4*>(p);
+          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            xo[2 * u] = bf16_lo(w4[u]);
+            xo[2 * u + 1] = bf16_hi(w4[u]);
+          }
+        }
+      }
+    } else {
+      const T* p = X + row * d;
+#pragma unroll
+      for (int q = 0; q < H; ++q) {
+        const int t = h * H + q;
+        xo[q] = t < d ? widen<T>(p[t]) : 0.f;
+      }
+    }
+  };
+  double Jacc = 0.0;
+  int64_t ucnt = 0, pcnt = 0;
+  const int64_t ntile = (n + 31) >> 5;
+  const int64_t tstride = (int64_t)gridDim.x * 4;
+  int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  float xnext[H];
+  // rows past n read the last row (their results are not used)
+  load_x(min((tile << 5) + pc, n - 1), xnext);
+  for (; tile < ntile; tile += tstride) {
+    const int64_t i = (tile << 5) + pc;
+    const bool valid = i < n;
+    float x[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) x[q] = xnext[q];
+    // rows of this wave's next tile, loaded while this one computes
+    load_x(min(((tile + tstride) << 5) + pc, n - 1), xnext);
+    // the point as the B operand (BF16 data is exact; FP32 data rounds to
+    // nearest even, two values per instruction)
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    constexpr int HP = (H + 1) / 2;  // packed pairs
+    uint32_t xw[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int q = 0; q < HP; ++q) {
+      const f32x2 pr = {x[2 * q], 2 * q + 1 < H ? x[2 * q + 1] : 0.f};
+      xw[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, bf16x2));
+    }
+    float s2 = 0.f, r2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < HP; ++q) {
+      const float lo = bf16_lo(xw[q]), hi = bf16_hi(xw[q]);
+      s2 = __builtin_fmaf(lo, lo, s2);
+      s2 = __builtin_fmaf(hi, hi, s2);
+      if constexpr (sizeof(T) == 4) {
+        const float r0 = x[2 * q] - lo;  // exact
+        r2 = __builtin_fmaf(r0, r0, r2);
+        if (2 * q + 1 < H) {
+          const float r1 = x[2 * q + 1] - hi;
+          r2 = __builtin_fmaf(r1, r1, r2);
+        }
+      }
+    }
+    // norms for the band (the hardware square root is within an ulp; the 1%
+    // factor covers it)
+    const float xn =
+        __builtin_amdgcn_sqrtf(s2 + __int_as_float(other_half(__float_as_int(s2), h))) * 1.01f;
+    float xr = 0.f;
+    if constexpr (sizeof(T) == 4)
+      xr = __builtin_amdgcn_sqrtf(r2 + __int_as_float(other_half(__float_as_int(r2), h))) * 1.01f;
+    const v8bf xv = __builtin_bit_cast(v8bf, xw);
+    int m1 = INT_MAX, m2 = INT_MAX, m3 = INT_MAX;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const v16f acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t], xv, bias[t], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        // the value part drops BG bits already here, so that the switch to the
+        // center index below cannot reorder keys whose value parts differ
+        const int kv = (__float_as_int(acc[r]) & ~GM) | (16 * t + r);
+        m3 = med3_i32(m2, kv, m3);
+        m2 = med3_i32(m1, kv, m2);
+        m1 = min(m1, kv);
+      }
+    }
+    auto glob = [&](int key) {
+      const int l = key & LM;
+      return (key & ~GM) | (32 * (l >> 4) + 8 * ((l & 15) >> 2) + 4 * h + (l & 3));
+    };
+    int g1 = glob(m1), g2 = glob(m2), g3 = glob(m3);
+    {
+      const int ov[3] = {other_half(g1, h), other_half(g2, h), other_half(g3, h)};
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        g3 = med3_i32(g2, ov[u], g3);
+        g2 = med3_i32(g1, ov[u], g2);
+        g1 = min(g1, ov[u]);
+      }
+    }
+    int bi = g1 & GM;
+    const int b2 = g2 & GM;
+    const float v1 = __int_as_float(g1 & ~GM), v2 = __int_as_float(g2 & ~GM),
+                v3 = __int_as_float(g3 & ~GM);
+    // two screened scores differ from their exact values by at most E2 together
+    const float E2 = 2.f * xn * dcn + 4.f * xr * cmax +
+                     2.f * ea * (cmax * cmax + B + 2.f * xn * cmax);
+    auto apart = [&](float lo, float hi) {
+      return (hi - lo) > E2 + delta * (fabsf(hi) + fabsf(lo));
+    };
+    // certain: the best beats every other center; pair: the best is one of the best two
+    const bool certain = k == 1 || (bi < k && apart(v1, v2));
+    const bool pair = valid && !certain && bi < k && b2 < k && (k == 2 || apart(v1, v3));
+    const bool full = valid && !certain && !pair;
+    if (bi >= k) bi = 0;
+    auto dist64 = [&](int j) {  // FP64 direct form over this lane's dims (zero past d)
+      const double* cj = cs + j * KD + h * H;
+      double p = 0.0;
+#pragma unroll
+      for (int q = 0; q < H; ++q) {
+        const double e = (double)x[q] - cj[q];
+        p = __builtin_fma(e, e, p);
+      }
+      return p;
+    };
+    auto both = [&](double v) {  // the sum over the two lane halves
+      const int lo = other_half((int)(uint32_t)__double_as_longlong(v), h);
+      const int hi = other_half((int)(uint32_t)((uint64_t)__double_as_longlong(v) >> 32), h);
+      return v + __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+    };
+    double p1 = dist64(bi);
+    if (__ballot(pair)) {
+      // the second candidate's FP64 distance decides (lowest index on ties)
+      const double p2 = dist64(pair ? b2 : 0);
+      const double D1p = both(p1), D2p = both(p2);
+      if (pair && (D2p < D1p || (D2p == D1p && b2 < bi))) {
+        bi = b2;
+        p1 = p2;
+      }
+      pcnt += __popcll(__ballot(pair && h == 0));
+    }
+    if (__ballot(full)) {
+      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi, KD);
+      const int bfull = __shfl(bi, pc);
+      if (full) {
+        bi = bfull < k ? bfull : 0;
+        p1 = dist64(bi);
+      }
+    }
+    if (valid) {
+      // each lane half adds its dims' part of the point's distance to J
+      Jacc += p1;
+      if (h == 0 && labels) labels[i] = bi;
+      if (update) {
+        unsigned long long* Sr = S + (int64_t)bi * (d + 1);
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+          const int dim = h * H + q;
+          if (FULL || dim < d) {
+            const int qv = __float2int_rn(x[q] * scale);
+            atomicAdd(&Sr[dim], (unsigned long long)(long long)qv);
+          }
+        }
+        if (h == 0) atomicAdd(&Sr[d], 1ull);
+      }
+    }
+  }
+  __syncthreads();
+  if (update) flush_sums(S, k, d, slots);
+  block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
+}
 
 // The BF16 screen of all points.  A block (4 waves) takes 4*PT tiles of 32
 // points; each wave keeps its rows as the B operand of 32x32x16 BF16 MFMAs in
@@ -2589,6 +2846,26 @@ static void visit_mfma(int kd, int nt, F&& f) {
   }
 }
 
+template <typename T, int KD, bool FULL, typename F>
+static void visit_fscreen_nt(int nt, F&& f) {
+  switch (nt) {
+    case 1: f(k_fused_screen<T, KD, 1, FULL>); break;
+    case 2: f(k_fused_screen<T, KD, 2, FULL>); break;
+    case 3: f(k_fused_screen<T, KD, 3, FULL>); break;
+    default: f(k_fused_screen<T, KD, 4, FULL>); break;
+  }
+}
+
+template <typename T, typename F>
+static void visit_fscreen(int kd, int nt, bool full, F&& f) {
+  switch (kd) {
+    case 2: full ? visit_fscreen_nt<T, 2, true>(nt, f) : visit_fscreen_nt<T, 2, false>(nt, f); break;
+    case 4: full ? visit_fscreen_nt<T, 4, true>(nt, f) : visit_fscreen_nt<T, 4, false>(nt, f); break;
+    case 8: full ? visit_fscreen_nt<T, 8, true>(nt, f) : visit_fscreen_nt<T, 8, false>(nt, f); break;
+    default: full ? visit_fscreen_nt<T, 16, true>(nt, f) : visit_fscreen_nt<T, 16, false>(nt, f); break;
+  }
+}
+
 template <typename T, typename F>
 static void visit_fused(int dmax, F&& f) {
   switch (dmax) {
@@ -2657,6 +2934,7 @@ static int64_t plan_blocks(const PassPlan& p, int cus) {
   if (p.bf16)
     visit_screen<T>(p.ks,
                     [&](auto kern) { r = resident_blocks(kern, 0, cus, screen_threads(p.ks)); });
+  else if (p.fscreen) visit_fscreen<T>(p.kd, p.nt, p.kd == p.d, f);
   else if (p.mfma) visit_mfma<T>(p.kd, p.nt, f);
   else if (p.fused) visit_fused<T>(p.dmax, f);
   else if (p.dmax) visit_tiled<T>(p.dmax, f);
@@ -2684,6 +2962,18 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
   if (p.bf16) {
     work = (rows + kScreenPoints - 1) / kScreenPoints;
+  } else if (precision == 0 && d <= 16 && k <= 128 &&
+             kk * (size_t)p.dmax * 8 + kk * (dd + 1) * 8 <= budget) {
+    // small d: the fused pass scores on the BF16 matrix cores (certified), which
+    // run beside the key updates; the FP32 MFMA pass stays for precision FP32
+    p.fscreen = true;
+    p.fused = true;
+    p.ks = 1;
+    p.kd = p.dmax;
+    p.d = d;
+    p.nt = (k + 31) / 32;
+    p.lds_assign = kk * (size_t)p.kd * 8 + kk * (dd + 1) * 8;
+    work = ((rows + 31) / 32 + 3) / 4;
   } else if (d <= 32 && k <= 128 && lds_mfma <= budget) {
     p.mfma = true;
     p.fused = true;
@@ -2692,7 +2982,7 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
     p.lds_assign = lds_mfma;
     work = ((rows + 31) / 32 + 3) / 4;
   }
-  if (!p.mfma) {
+  if (!p.mfma && !p.fscreen) {
     p.fused = !p.bf16 && p.dmax != 0 && lds_fused <= budget;
     const int64_t tile_pts = 256LL * p.ppt;
     if (!p.bf16) work = (rows + tile_pts - 1) / tile_pts;
@@ -2726,8 +3016,21 @@ static void dispatch_fused(const PassBufs& b, const PassPlan& p, bool update,
                        b.n, b.d, b.k, b.cw, b.cn, b.c64, (const PassState*)b.st, gate,
                        update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
   };
-  if (p.mfma) visit_mfma<T>(p.kd, p.nt, launch);
-  else visit_fused<T>(p.dmax, launch);
+  if (p.fscreen) {
+    // the whole-row kernel loads half rows as aligned vectors
+    const size_t vb = (size_t)(p.kd / 2) * sizeof(T), al = vb < 16 ? vb : 16;
+    const bool full = p.kd == b.d && (reinterpret_cast<uintptr_t>(b.X) % al) == 0;
+    visit_fscreen<T>(p.kd, p.nt, full, [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
+                         (const T*)b.X, b.n, b.d, b.k, (const uint16_t*)b.cb16,
+                         (const float*)b.cnB, (const double*)b.c64, (const PassState*)b.st,
+                         gate, update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
+    });
+  } else if (p.mfma) {
+    visit_mfma<T>(p.kd, p.nt, launch);
+  } else {
+    visit_fused<T>(p.dmax, launch);
+  }
 }
 
 template <typename T>
@@ -2844,7 +3147,7 @@ hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStrea
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)b.k), dim3(256), 0, s, b.slots,
                        sorted ? b.jslots : nullptr, b.k, b.d, b.st, gate, update ? 1 : 0, b.c64,
                        b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out,
-                       p.bf16 ? b.cb16 : nullptr, p.bf16 ? b.cnB : nullptr, p.ks * 16,
+                       copy16(p) ? b.cb16 : nullptr, copy16(p) ? b.cnB : nullptr, p.ks * 16,
                        (const double*)b.Jpart, (const long long*)b.upart, nb, b.J_hist,
                        b.shift_hist);
   } else {

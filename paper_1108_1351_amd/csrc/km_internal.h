@@ -148,9 +148,11 @@ struct PassBufs {
 // Geometry chosen once per (rows, d, k): fused or split path and block counts.
 struct PassPlan {
   bool bf16;         // split pass with the BF16 MFMA screen (x.c^T as 32x32x16 tiles)
+  bool fscreen;      // fused pass on the BF16 MFMA screen (d <= 16, k <= 128)
   int ks;            // 16-dim K steps of the BF16 screen
   bool mfma;         // fused pass on FP32 MFMA (x.c^T as 32x32x2 tiles)
-  int kd, nt;        // padded dims and 32-center tiles of the MFMA kernel
+  int kd, nt;        // padded dims and 32-center tiles of the MFMA kernels
+  int d;             // dims of the rows (the fused screen has a kernel for d == kd)
   bool fused;
   int dmax;          // register tile of a row (0: generic)
   int ppt;           // points per thread
@@ -161,6 +163,11 @@ struct PassPlan {
   size_t lds_assign;
   int ktile;         // centers per LDS tile (split assign)
 };
+
+// The pass keeps a BF16 copy of the centers (prep_bf16, then the finalize).
+inline bool copy16(const PassPlan& p) { return p.bf16 || p.fscreen; }
+// The stage statistics include max ||x||^2 (split paths and the BF16 screens).
+inline bool wants_norms(const PassPlan& p) { return !p.fused || p.fscreen; }
 
 // Batched passes (kernels.hip).  A group shares the element type and the
 // register tile (dmax, points per thread); bi/hd are device pointers.

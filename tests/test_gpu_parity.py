@@ -89,6 +89,32 @@ def test_step_parity(d, k):
     assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
 
 
+SMALL_D = [(1, 5), (2, 8), (4, 32), (5, 7), (8, 64), (16, 64), (16, 128), (3, 100)]
+
+
+@pytest.mark.parametrize("d,k", SMALL_D)
+@pytest.mark.parametrize("precision", ["auto", "fp32"])
+def test_small_d_fused_paths(d, k, precision):
+    """d <= 16, k <= 128: the fused pass on the BF16 screen (auto) and on FP32
+    MFMA (precision fp32) give the oracle's labels, J and new centers."""
+    n = 20_011
+    print(f"[small-d {precision}] n={n} d={d} k={k}", flush=True)
+    Xh = _mixture(n, d, min(k, 40), seed=d * 31 + k)
+    C = _centers_from(Xh, k, seed=k + 5, jitter=0.5)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda(), precision=precision)
+    ref = oracle.step(Xh, C)
+    lab = out["labels"].cpu().numpy()
+    ex = exempt_mask(Xh, C)
+    assert np.array_equal(lab[~ex], ref.labels[~ex])
+    assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
+    if np.array_equal(lab, ref.labels):
+        assert np.array_equal(out["N"].cpu().numpy(), ref.N)
+        assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9, name="C_new")
+    lab2, J2, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision=precision)
+    assert np.array_equal(lab2.cpu().numpy()[~ex], ref.labels[~ex])
+    assert abs(J2 - ref.J) <= 1e-12 * ref.J
+
+
 def test_step_bf16_input():
     Xh = _mixture(20_011, 64, 40, seed=3, dtype="bf16")
     C = _centers_from(Xh, 40, seed=4)
@@ -320,34 +346,35 @@ def _far_centers(d, count, seed):
     return 40.0 + rng.normal(0, 3.0, size=(count, d))
 
 
+@pytest.mark.parametrize("d,precision", [(128, "bf16_rerank"), (16, "auto")])
 @pytest.mark.parametrize("extra", [0, 38])
 @pytest.mark.parametrize("m", [0, 5, 40, 100])
-def test_bf16_screen_band_covers_center_rounding(m, extra):
+def test_bf16_screen_band_covers_center_rounding(m, extra, d, precision):
     """Adversarial BF16 rounding of the centers.  x = (1, ..., 1); c1 and c2 are
     constant vectors just below and just above a BF16 rounding midpoint of -2c,
     so every entry of the screen's copy of c1 rounds up by almost half an ulp
     and every entry of c2's rounds down.  c1 is the nearer center, but the
     screen's scores put c2 ahead by nearly 128 * 2^-6 = 2, more than half of
     the worst-case error of two scores: only a band that covers the full
-    rounding of both centers sends the point to the re-rank."""
-    d = 128
+    rounding of both centers sends the point to the re-rank.  d = 16 runs the
+    fused small-d pass, d = 128 the split screen."""
     v1, v2 = 1 + (m + 0.49) * 2.0 ** -7, 1 + (m + 0.51) * 2.0 ** -7
     C = np.vstack([np.full((1, d), v1), np.full((1, d), v2), _far_centers(d, extra, m)])
     Xh = synth_bf16(np.ones((64, d)))
     ref = oracle.step(Xh, C)
     assert (ref.labels == 0).all()
-    print(f"[bf16 band] m={m} k={len(C)}", flush=True)
-    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="bf16_rerank")
+    print(f"[bf16 band] d={d} m={m} k={len(C)}", flush=True)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision=precision)
     assert (lab.cpu().numpy() == 0).all()
     assert abs(J - ref.J) <= 1e-9 * ref.J
 
 
+@pytest.mark.parametrize("d,precision", [(128, "bf16_rerank"), (16, "auto")])
 @pytest.mark.parametrize("extra", [0, 38])
-def test_bf16_screen_band_covers_fp32_data_rounding(extra):
+def test_bf16_screen_band_covers_fp32_data_rounding(extra, d, precision):
     """FP32 data whose BF16 roundings all point one way: with c1 = -c2 = 0.5
     (exact in BF16), the rounded point prefers c1 by 0.78 while c2 is nearer;
-    the band term 4 ||x^ - x|| max||c|| (about 1.0 here) catches it."""
-    d = 128
+    the band term 4 ||x^ - x|| max||c|| (about 1.0 at d = 128) catches it."""
     x = np.empty(d, np.float32)
     x[0::2] = np.float32(1 + 0.51 * 2.0 ** -7)
     x[1::2] = np.float32(-(1 + 0.49 * 2.0 ** -7))
@@ -356,8 +383,8 @@ def test_bf16_screen_band_covers_fp32_data_rounding(extra):
     C = np.vstack([np.full((1, d), 0.5), np.full((1, d), -0.5), _far_centers(d, extra, 3)])
     ref = oracle.step(Xh, C)
     assert (ref.labels == 1).all()
-    print(f"[bf16 band f32] k={len(C)}", flush=True)
-    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="bf16_rerank")
+    print(f"[bf16 band f32] d={d} k={len(C)}", flush=True)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision=precision)
     assert (lab.cpu().numpy() == 1).all()
     assert abs(J - ref.J) <= 1e-9 * ref.J
 
