@@ -10,12 +10,11 @@ per second of the whole job: k*(m*Q_f + n*Q_s) + k*n evaluations per fit
 fit's wall time.
 
 The roofline object covers the dominant kernel, the slow stage's assignment
-kernel (for BF16 data, its BF16 MFMA screen): its duration is measured live
-with HIP events on the stream it runs on (the library's pass profiler).  Its
-algorithmic work per launch is 2*n*k*d flops and n*d*s bytes (s = bytes per
-element); the bound is whichever of HBM bandwidth and the arithmetic peak
-(FP32 vector for the FP32 kernels, dense BF16 MFMA for the screen) allows
-less.  The CPU baseline is the FP64 oracle timed on a bounded sample of the
+kernel (for BF16 data, its BF16 MFMA screen): its duration is measured live with HIP events on the stream it
+runs on (the library's pass profiler).  Its algorithmic work per launch is
+2*n*k*d flops and n*d*s bytes (s = bytes per element of X); the bound is
+whichever of HBM bandwidth and the arithmetic peak (dense BF16 MFMA for the
+screen, FP32 for the FP32 kernels) allows less.  The CPU baseline is the FP64 oracle timed on a bounded sample of the
 same workload on the host's cores.
 """
 from __future__ import annotations
@@ -242,6 +241,8 @@ def main() -> int:
     rows = prof["rows"][1] / max(1, launches)
     flops = 2.0 * rows * w.k * w.d
     algo_bytes = rows * w.d * (4 if w.dtype == "f32" else 2)
+    # the pass the library plans at auto precision: the split BF16 screen (BF16
+    # data, d >= 32) or the FP32 kernels
     bf16_screen = w.dtype == "bf16" and w.d >= 32
     peak_flops = PEAK_BF16_TFLOPS if bf16_screen else PEAK_FP32_TFLOPS
     traffic = read_traffic(w.name)
@@ -250,13 +251,16 @@ def main() -> int:
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     else:
         achieved = flops / avg_s / 1e12
-        roofline = {"bound": "mfma" if bf16_screen else "alu", "achieved": achieved,
-                    "peak": peak_flops, "unit": "TFLOP/s"}
+        roofline = {"bound": "mfma" if bf16_screen else "alu",
+                    "achieved": achieved, "peak": peak_flops, "unit": "TFLOP/s"}
+    if bf16_screen:
+        kernel = ("slow-stage BF16 MFMA screen (slot-pair top-2 keys, certified candidates, "
+                  "FP32/FP64 re-rank)")
+    else:
+        kernel = "slow-stage assignment kernel (fused assign + cluster sums)"
     roofline.update({
         "frac": roofline["achieved"] / roofline["peak"], "traffic": traffic,
-        "kernel": ("slow-stage BF16 MFMA screen (slot-pair top-2 keys, certified candidates, FP32/FP64 re-rank)"
-                   if bf16_screen else
-                   "slow-stage assignment kernel (fused assign + cluster sums)"),
+        "kernel": kernel,
         "launches": launches, "avg_launch_us": avg_s * 1e6,
         "flops_per_launch": flops, "algo_bytes_per_launch": algo_bytes,
         "achieved_TFLOPs": flops / avg_s / 1e12, "algo_hbm_GBs": algo_bytes / avg_s / 1e9})
@@ -272,7 +276,9 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if w.dtype == "f32" else "bf16",
+        # scores on BF16 MFMA (FP32 accumulation) for the screen, else FP32;
+        # decisions certified in FP32/FP64
+        "dtype": "bf16" if bf16_screen else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k,
                    "subset_frac": w.subset_frac, "max_iter": w.max_iter, "tol": w.tol,

@@ -2951,7 +2951,10 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   const size_t kk = (size_t)k, dd = (size_t)d;
   // BF16 screen: asked for, or automatic for BF16 data with d >= 32 (precision
   // codes follow km_precision: 0 auto, 1 FP32, 2 BF16 screen)
-  p.bf16 = d <= 256 && (precision == 2 || (precision == 0 && dtype == 1 && d >= 32));
+  const bool screen = precision == 2 || (precision == 0 && dtype == 1 && d >= 32);
+  const bool small = d <= 16 && k <= 128 &&
+                     kk * (size_t)p.dmax * 8 + kk * (dd + 1) * 8 <= budget;
+  p.bf16 = d <= 256 && screen && !small;
   if (p.bf16) {
     p.ks = d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 4 : d <= 128 ? 8 : 16;
     p.dmax = 0;
@@ -2962,10 +2965,11 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
   if (p.bf16) {
     work = (rows + kScreenPoints - 1) / kScreenPoints;
-  } else if (precision == 0 && d <= 16 && k <= 128 &&
-             kk * (size_t)p.dmax * 8 + kk * (dd + 1) * 8 <= budget) {
-    // small d: the fused pass scores on the BF16 matrix cores (certified), which
-    // run beside the key updates; the FP32 MFMA pass stays for precision FP32
+  } else if (screen && small) {
+    // small d, BF16 screen asked for: the fused pass scores on the BF16 matrix
+    // cores (certified).  Where clusters are close relative to the BF16 band
+    // (||x|| ||c|| 2^-7), many points need FP64 decisions, so auto precision
+    // keeps the FP32 MFMA pass.
     p.fscreen = true;
     p.fused = true;
     p.ks = 1;

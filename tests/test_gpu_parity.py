@@ -93,10 +93,11 @@ SMALL_D = [(1, 5), (2, 8), (4, 32), (5, 7), (8, 64), (16, 64), (16, 128), (3, 10
 
 
 @pytest.mark.parametrize("d,k", SMALL_D)
-@pytest.mark.parametrize("precision", ["auto", "fp32"])
+@pytest.mark.parametrize("precision", ["bf16_rerank", "fp32"])
 def test_small_d_fused_paths(d, k, precision):
-    """d <= 16, k <= 128: the fused pass on the BF16 screen (auto) and on FP32
-    MFMA (precision fp32) give the oracle's labels, J and new centers."""
+    """d <= 16, k <= 128: the fused pass on the BF16 screen (precision
+    bf16_rerank) and on FP32 MFMA (fp32, also the auto choice) give the oracle's
+    labels, J and new centers."""
     n = 20_011
     print(f"[small-d {precision}] n={n} d={d} k={k}", flush=True)
     Xh = _mixture(n, d, min(k, 40), seed=d * 31 + k)
@@ -302,7 +303,7 @@ def test_near_duplicate_centers_resolved_in_fp64(d, k):
 # ------------------------------------------------------------- BF16 screen
 @pytest.mark.parametrize("d,k,dtype", [(32, 64, "bf16"), (128, 1024, "bf16"), (100, 37, "bf16"),
                                        (64, 300, "f32"), (256, 50, "bf16"), (16, 64, "f32"),
-                                       (200, 129, "f32")])
+                                       (200, 129, "f32"), (16, 300, "f32"), (8, 200, "bf16")])
 def test_bf16_screen_step_parity(d, k, dtype):
     """BF16 MFMA screen, certified candidates, FP32 re-rank and FP64 decisions."""
     n = 12_289
@@ -346,10 +347,10 @@ def _far_centers(d, count, seed):
     return 40.0 + rng.normal(0, 3.0, size=(count, d))
 
 
-@pytest.mark.parametrize("d,precision", [(128, "bf16_rerank"), (16, "auto")])
+@pytest.mark.parametrize("d", [128, 16])
 @pytest.mark.parametrize("extra", [0, 38])
 @pytest.mark.parametrize("m", [0, 5, 40, 100])
-def test_bf16_screen_band_covers_center_rounding(m, extra, d, precision):
+def test_bf16_screen_band_covers_center_rounding(m, extra, d):
     """Adversarial BF16 rounding of the centers.  x = (1, ..., 1); c1 and c2 are
     constant vectors just below and just above a BF16 rounding midpoint of -2c,
     so every entry of the screen's copy of c1 rounds up by almost half an ulp
@@ -357,21 +358,21 @@ def test_bf16_screen_band_covers_center_rounding(m, extra, d, precision):
     screen's scores put c2 ahead by nearly 128 * 2^-6 = 2, more than half of
     the worst-case error of two scores: only a band that covers the full
     rounding of both centers sends the point to the re-rank.  d = 16 runs the
-    fused small-d pass, d = 128 the split screen."""
+    fused small-d screen, d = 128 the split screen."""
     v1, v2 = 1 + (m + 0.49) * 2.0 ** -7, 1 + (m + 0.51) * 2.0 ** -7
     C = np.vstack([np.full((1, d), v1), np.full((1, d), v2), _far_centers(d, extra, m)])
     Xh = synth_bf16(np.ones((64, d)))
     ref = oracle.step(Xh, C)
     assert (ref.labels == 0).all()
     print(f"[bf16 band] d={d} m={m} k={len(C)}", flush=True)
-    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision=precision)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="bf16_rerank")
     assert (lab.cpu().numpy() == 0).all()
     assert abs(J - ref.J) <= 1e-9 * ref.J
 
 
-@pytest.mark.parametrize("d,precision", [(128, "bf16_rerank"), (16, "auto")])
+@pytest.mark.parametrize("d", [128, 16])
 @pytest.mark.parametrize("extra", [0, 38])
-def test_bf16_screen_band_covers_fp32_data_rounding(extra, d, precision):
+def test_bf16_screen_band_covers_fp32_data_rounding(extra, d):
     """FP32 data whose BF16 roundings all point one way: with c1 = -c2 = 0.5
     (exact in BF16), the rounded point prefers c1 by 0.78 while c2 is nearer;
     the band term 4 ||x^ - x|| max||c|| (about 1.0 at d = 128) catches it."""
@@ -384,7 +385,7 @@ def test_bf16_screen_band_covers_fp32_data_rounding(extra, d, precision):
     ref = oracle.step(Xh, C)
     assert (ref.labels == 1).all()
     print(f"[bf16 band f32] d={d} k={len(C)}", flush=True)
-    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision=precision)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="bf16_rerank")
     assert (lab.cpu().numpy() == 1).all()
     assert abs(J - ref.J) <= 1e-9 * ref.J
 
