@@ -1181,6 +1181,88 @@ __device__ __forceinline__ int med3_i32(int a, int b, int c) {
   return max(min(a, b), min(max(a, b), c));
 }
 
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// The value x of the lane in the other half of the wave (lane ^ 32): one
+// permlane32 swap, no LDS traffic.  h is the lane's half (lane >> 5).
+__device__ __forceinline__ int other_half(int x, int h) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return h ? (int)r[0] : (int)r[1];
+}
+
+// v + (v of the lane in the other half): the sum over the two lane halves.
+__device__ __forceinline__ double sum_halves(double v, int h) {
+  const long long b = __double_as_longlong(v);
+  const int lo = other_half((int)(uint32_t)b, h);
+  const int hi = other_half((int)(uint32_t)((uint64_t)b >> 32), h);
+  return v + __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ float sum_halves(float v, int h) {
+  return v + __int_as_float(other_half(__float_as_int(v), h));
+}
+
+// Dims [hH, hH + H) of row `row` (H = KD/2) into registers.  FULL (d == KD):
+// one aligned vector load per half row (the launcher checks the alignment of
+// X); otherwise element loads with bounds (zero past d).
+template <typename T, int KD, bool FULL>
+__device__ __forceinline__ void load_half_row(const T* __restrict__ X, int64_t row, int d, int h,
+                                              float (&xo)[KD / 2]) {
+  constexpr int H = KD / 2;
+  if constexpr (FULL) {
+    const T* p = X + row * KD + h * H;
+    if constexpr (sizeof(T) == 4) {
+      if constexpr (H == 1) {
+        xo[0] = p[0];
+      } else if constexpr (H == 2) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        xo[0] = v.x; xo[1] = v.y;
+      } else {
+#pragma unroll
+        for (int q = 0; q < H; q += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(p + q);
+          xo[q] = v.x; xo[q + 1] = v.y; xo[q + 2] = v.z; xo[q + 3] = v.w;
+        }
+      }
+    } else {
+      if constexpr (H == 1) {
+        xo[0] = widen<T>(p[0]);
+      } else if constexpr (H == 2) {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+        xo[0] = bf16_lo(w); xo[1] = bf16_hi(w);
+      } else if constexpr (H == 4) {
+        const uint2 w = *reinterpret_cast<const uint2*>(p);
+        xo[0] = bf16_lo(w.x); xo[1] = bf16_hi(w.x); xo[2] = bf16_lo(w.y); xo[3] = bf16_hi(w.y);
+      } else {
+#pragma unroll
+        for (int q = 0; q < H; q += 8) {
+          const uint4 w = *reinterpret_cast<const uint4*>(p + q);
+          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            xo[q + 2 * u] = bf16_lo(w4[u]);
+            xo[q + 2 * u + 1] = bf16_hi(w4[u]);
+          }
+        }
+      }
+    }
+  } else {
+    const T* p = X + row * d;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      const int t = h * H + q;
+      xo[q] = t < d ? widen<T>(p[t]) : 0.f;
+    }
+  }
+}
+
+// Whether the whole-row kernels may load half rows of X as aligned vectors.
+template <typename T>
+inline bool full_rows_ok(int kd, int d, const void* X) {
+  const size_t vb = (size_t)(kd / 2) * sizeof(T), al = vb < 16 ? vb : 16;
+  return kd == d && (reinterpret_cast<uintptr_t>(X) % al) == 0;
+}
+
 // Dims [h*H, h*H + H) of a row into registers; zero beyond d and for invalid rows.
 template <typename T, int H>
 __device__ __forceinline__ void load_half(const T* __restrict__ row, int d, int h, bool valid,
@@ -1281,11 +1363,13 @@ __device__ __forceinline__ int64_t mfma_fp64_check(bool unc, const float (&x)[H]
 // each tile of 32 centers one chain of 32x32x2 MFMAs gives every lane 16
 // squared distances ||x||^2 + ||c||^2 - 2 x.c of its point (lane and lane^32
 // hold the two halves of the 32 centers; the last K=2 step adds ||x||^2 and
-// ||c||^2).  The best two are kept as integer keys (distance bits with the
-// center index in the low bits, so one min3/med3 ranks value and index
-// together); a rigorous error bound certifies the best center or sends the
-// point to the FP64 check.  Cluster sums go to LDS, then to the slots.
-template <typename T, int KD, int NT>
+// ||c||^2).  The best three are kept as integer keys (distance bits with the
+// center index in the low bits, so one min/med3 ranks value and index
+// together); a rigorous error bound certifies the best center, decides close
+// pairs in FP64, or sends the point to the FP64 check.  Cluster sums go to LDS,
+// then to the slots.  J in FP64, each lane half adding its dims' part.
+// FULL: d == KD (whole half rows, no padded dims).
+template <typename T, int KD, int NT, bool FULL>
 __global__ __launch_bounds__(256) void k_fused_mfma(
     const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cw,
     const float* __restrict__ cn, const double* __restrict__ c64, const PassState* __restrict__ st,
@@ -1297,12 +1381,12 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
   constexpr int BG = BL + 1;                            // bits of a center index (32*NT centers)
   constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
   extern __shared__ __align__(16) unsigned char smem[];
-  double* cs = reinterpret_cast<double*>(smem);  // [k][d+1] FP64 centers
-  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * (d + 1));
+  double* cs = reinterpret_cast<double*>(smem);  // [k][KD] FP64 centers, zero past d
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * KD);  // [k][d+1]
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < k * d; e += 256) {
-    const int j = e / d, t = e - j * d;
-    cs[(int64_t)j * (d + 1) + t] = c64[e];
+  for (int e = threadIdx.x; e < k * KD; e += 256) {
+    const int j = e / KD, t = e - j * KD;
+    cs[e] = t < d ? c64[(int64_t)j * d + t] : 0.0;
   }
   if (update)
     for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
@@ -1330,24 +1414,20 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
   const int64_t tstride = (int64_t)gridDim.x * 4;
   int64_t tile = (int64_t)blockIdx.x * 4 + wave;
   float xnext[H];
-  {
-    const int64_t i0 = (tile << 5) + pc;
-    load_half<T, H>(X + (i0 < n ? i0 : 0) * d, d, h, tile < ntile && i0 < n, xnext);
-  }
+  // rows past n read the last row (their results are not used)
+  load_half_row<T, KD, FULL>(X, min((tile << 5) + pc, n - 1), d, h, xnext);
   for (; tile < ntile; tile += tstride) {
     const int64_t i = (tile << 5) + pc;
     const bool valid = i < n;
     float x[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) x[q] = xnext[q];
-    {  // rows of this wave's next tile, loaded while this one computes
-      const int64_t in = ((tile + tstride) << 5) + pc;
-      load_half<T, H>(X + (in < n ? in : 0) * d, d, h, tile + tstride < ntile && in < n, xnext);
-    }
+    // rows of this wave's next tile, loaded while this one computes
+    load_half_row<T, KD, FULL>(X, min(((tile + tstride) << 5) + pc, n - 1), d, h, xnext);
     float xs = 0.f;
 #pragma unroll
     for (int q = 0; q < H; ++q) xs = __builtin_fmaf(x[q], x[q], xs);
-    const float xn2 = xs + __shfl_xor(xs, 32);
+    const float xn2 = sum_halves(xs, h);
     const float bx = h == 0 ? xn2 : 1.f;
     int m1 = INT_MAX, m2 = INT_MAX, m3 = INT_MAX;
 #pragma unroll
@@ -1376,8 +1456,7 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
     };
     int g1 = glob(m1), g2 = glob(m2), g3 = glob(m3);
     {
-      const int o1 = __shfl_xor(g1, 32), o2 = __shfl_xor(g2, 32), o3 = __shfl_xor(g3, 32);
-      const int ov[3] = {o1, o2, o3};
+      const int ov[3] = {other_half(g1, h), other_half(g2, h), other_half(g3, h)};
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         g3 = med3_i32(g2, ov[u], g3);
@@ -1389,7 +1468,8 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
     const int b2 = g2 & GM;
     const float v1 = __int_as_float(g1 & ~GM), v2 = __int_as_float(g2 & ~GM),
                 v3 = __int_as_float(g3 & ~GM);
-    const float xn = sqrtf(xn2) * 1.0001f + cmax;
+    // the hardware square root is within an ulp; the 1e-4 factor covers it
+    const float xn = __builtin_amdgcn_sqrtf(xn2) * 1.0001f + cmax;
     const float E2 = 2.f * (KE * xn * xn + 1e-30f);
     // certain: the best beats every other center; pair: the best is one of the best two
     const bool certain = k == 1 || (bi < k && (v2 - v1) > E2 + delta * (fabsf(v2) + fabsf(v1)));
@@ -1397,63 +1477,45 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
                       (k == 2 || (v3 - v1) > E2 + delta * (fabsf(v3) + fabsf(v1)));
     const bool full = valid && !certain && !pair;
     if (bi >= k) bi = 0;
-    // FP64 squared distance to the best candidate (J), direct form, this lane's dims
-    double p1 = 0.0;
-    {
-      const double* c1 = cs + (int64_t)bi * (d + 1) + h * H;
+    auto dist64 = [&](int j) {  // FP64 direct form over this lane's dims (zero past d)
+      const double* cj = cs + j * KD + h * H;
+      double p = 0.0;
 #pragma unroll
-      for (int q = 0; q < H; ++q)
-        if (h * H + q < d) {
-          const double e = (double)x[q] - c1[q];
-          p1 = __builtin_fma(e, e, p1);
-        }
-    }
-    double D1 = p1 + __shfl_xor(p1, 32);
+      for (int q = 0; q < H; ++q) {
+        const double e = (double)x[q] - cj[q];
+        p = __builtin_fma(e, e, p);
+      }
+      return p;
+    };
+    double p1 = dist64(bi);
     if (__ballot(pair)) {
       // the second candidate's FP64 distance decides the pair (lowest index on ties)
-      const double* c2 = cs + (int64_t)(pair ? b2 : 0) * (d + 1) + h * H;
-      double p2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < H; ++q)
-        if (h * H + q < d) {
-          const double e = (double)x[q] - c2[q];
-          p2 = __builtin_fma(e, e, p2);
-        }
-      const double D2 = p2 + __shfl_xor(p2, 32);
+      const double p2 = dist64(pair ? b2 : 0);
+      const double D1 = sum_halves(p1, h), D2 = sum_halves(p2, h);
       if (pair && (D2 < D1 || (D2 == D1 && b2 < bi))) {
         bi = b2;
-        D1 = D2;
+        p1 = p2;
       }
       pcnt += __popcll(__ballot(pair && h == 0));
     }
     if (__ballot(full)) {
-      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi);
+      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi, KD);
       const int bfull = __shfl(bi, pc);
       if (full) {
         bi = bfull < k ? bfull : 0;
-        const double* c1 = cs + (int64_t)bi * (d + 1) + h * H;
-        p1 = 0.0;
-#pragma unroll
-        for (int q = 0; q < H; ++q)
-          if (h * H + q < d) {
-            const double e = (double)x[q] - c1[q];
-            p1 = __builtin_fma(e, e, p1);
-          }
+        p1 = dist64(bi);
       }
-      const double pf = p1 + __shfl_xor(p1, 32);
-      if (full) D1 = pf;
     }
     if (valid) {
-      if (h == 0) {
-        Jacc += D1;
-        if (labels) labels[i] = bi;
-      }
+      // each lane half adds its dims' part of the point's distance to J
+      Jacc += p1;
+      if (h == 0 && labels) labels[i] = bi;
       if (update) {
         unsigned long long* Sr = S + (int64_t)bi * (d + 1);
 #pragma unroll
         for (int q = 0; q < H; ++q) {
           const int dim = h * H + q;
-          if (dim < d) {
+          if (FULL || dim < d) {
             const int qv = __float2int_rn(x[q] * scale);
             atomicAdd(&Sr[dim], (unsigned long long)(long long)qv);
           }
@@ -1520,8 +1582,6 @@ __device__ __forceinline__ v8bf load8_bf16(const T* __restrict__ row, int t0, in
   }
 }
 
-__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
-__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 // Among candidate centers cand[0..nc) (wave-uniform loop bound ncmax), the
 // nearest to the lane's point: FP32 direct-form distances first, certified by
@@ -1705,13 +1765,6 @@ __device__ __forceinline__ int opaque_vgpr(int v) {
   return r;
 }
 
-// The value x of the lane in the other half of the wave (lane ^ 32): one
-// permlane32 swap, no LDS traffic.  h is the lane's half (lane >> 5).
-__device__ __forceinline__ int other_half(int x, int h) {
-  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-  return h ? (int)r[0] : (int)r[1];
-}
-
 // Marks v as used here (no instruction): keeps the code that computes it from
 // being sunk past this point by the optimizer.
 __device__ __forceinline__ void pin_here(int& v) { asm volatile("" : "+v"(v)); }
@@ -1774,52 +1827,7 @@ __global__ __launch_bounds__(256, 3) void k_fused_screen(
   const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f, scale = st->scale;
   const float ea = (float)(16 + 8) * 0x1p-23f * 1.01f;
   const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
-  // FULL: the half row is one aligned vector load (the launcher checks the
-  // alignment of X); otherwise element loads with bounds
-  auto load_x = [&](int64_t row, float (&xo)[H]) {
-    if constexpr (FULL) {
-      const T* p = X + row * KD + h * H;
-      if constexpr (sizeof(T) == 4) {
-        if constexpr (H == 1) {
-          xo[0] = p[0];
-        } else if constexpr (H == 2) {
-          const float2 v = *reinterpret_cast<const float2*>(p);
-          xo[0] = v.x; xo[1] = v.y;
-        } else {
-#pragma unroll
-          for (int q = 0; q < H; q += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(p + q);
-            xo[q] = v.x; xo[q + 1] = v.y; xo[q + 2] = v.z; xo[q + 3] = v.w;
-          }
-        }
-      } else {
-        if constexpr (H == 1) {
-          xo[0] = widen<T>(p[0]);
-        } else if constexpr (H == 2) {
-          const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
-          xo[0] = bf16_lo(w); xo[1] = bf16_hi(w);
-        } else if constexpr (H == 4) {
-          const uint2 w = *reinterpret_cast<const uint2*>(p);
-          xo[0] = bf16_lo(w.x); xo[1] = bf16_hi(w.x); xo[2] = bf16_lo(w.y); xo[3] = bf16_hi(w.y);
-        } else {
-          const uint4 w = *reinterpret_cast<const uint4*>(p);
-          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            xo[2 * u] = bf16_lo(w4[u]);
-            xo[2 * u + 1] = bf16_hi(w4[u]);
-          }
-        }
-      }
-    } else {
-      const T* p = X + row * d;
-#pragma unroll
-      for (int q = 0; q < H; ++q) {
-        const int t = h * H + q;
-        xo[q] = t < d ? widen<T>(p[t]) : 0.f;
-      }
-    }
-  };
+  auto load_x = [&](int64_t row, float (&xo)[H]) { load_half_row<T, KD, FULL>(X, row, d, h, xo); };
   double Jacc = 0.0;
   int64_t ucnt = 0, pcnt = 0;
   const int64_t ntile = (n + 31) >> 5;
@@ -1923,16 +1931,11 @@ __global__ __launch_bounds__(256, 3) void k_fused_screen(
       }
       return p;
     };
-    auto both = [&](double v) {  // the sum over the two lane halves
-      const int lo = other_half((int)(uint32_t)__double_as_longlong(v), h);
-      const int hi = other_half((int)(uint32_t)((uint64_t)__double_as_longlong(v) >> 32), h);
-      return v + __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-    };
     double p1 = dist64(bi);
     if (__ballot(pair)) {
       // the second candidate's FP64 distance decides (lowest index on ties)
       const double p2 = dist64(pair ? b2 : 0);
-      const double D1p = both(p1), D2p = both(p2);
+      const double D1p = sum_halves(p1, h), D2p = sum_halves(p2, h);
       if (pair && (D2p < D1p || (D2p == D1p && b2 < bi))) {
         bi = b2;
         p1 = p2;
@@ -2825,24 +2828,24 @@ static int pick_ppt(int dmax) {
 }
 
 // Calls f with the kernel instance for the plan (function pointer).
-template <typename T, int KD, typename F>
+template <typename T, int KD, bool FULL, typename F>
 static void visit_mfma_nt(int nt, F&& f) {
   switch (nt) {
-    case 1: f(k_fused_mfma<T, KD, 1>); break;
-    case 2: f(k_fused_mfma<T, KD, 2>); break;
-    case 3: f(k_fused_mfma<T, KD, 3>); break;
-    default: f(k_fused_mfma<T, KD, 4>); break;
+    case 1: f(k_fused_mfma<T, KD, 1, FULL>); break;
+    case 2: f(k_fused_mfma<T, KD, 2, FULL>); break;
+    case 3: f(k_fused_mfma<T, KD, 3, FULL>); break;
+    default: f(k_fused_mfma<T, KD, 4, FULL>); break;
   }
 }
 
 template <typename T, typename F>
-static void visit_mfma(int kd, int nt, F&& f) {
+static void visit_mfma(int kd, int nt, bool full, F&& f) {
   switch (kd) {
-    case 2: visit_mfma_nt<T, 2>(nt, f); break;
-    case 4: visit_mfma_nt<T, 4>(nt, f); break;
-    case 8: visit_mfma_nt<T, 8>(nt, f); break;
-    case 16: visit_mfma_nt<T, 16>(nt, f); break;
-    default: visit_mfma_nt<T, 32>(nt, f); break;
+    case 2: full ? visit_mfma_nt<T, 2, true>(nt, f) : visit_mfma_nt<T, 2, false>(nt, f); break;
+    case 4: full ? visit_mfma_nt<T, 4, true>(nt, f) : visit_mfma_nt<T, 4, false>(nt, f); break;
+    case 8: full ? visit_mfma_nt<T, 8, true>(nt, f) : visit_mfma_nt<T, 8, false>(nt, f); break;
+    case 16: full ? visit_mfma_nt<T, 16, true>(nt, f) : visit_mfma_nt<T, 16, false>(nt, f); break;
+    default: full ? visit_mfma_nt<T, 32, true>(nt, f) : visit_mfma_nt<T, 32, false>(nt, f); break;
   }
 }
 
@@ -2935,7 +2938,7 @@ static int64_t plan_blocks(const PassPlan& p, int cus) {
     visit_screen<T>(p.ks,
                     [&](auto kern) { r = resident_blocks(kern, 0, cus, screen_threads(p.ks)); });
   else if (p.fscreen) visit_fscreen<T>(p.kd, p.nt, p.kd == p.d, f);
-  else if (p.mfma) visit_mfma<T>(p.kd, p.nt, f);
+  else if (p.mfma) visit_mfma<T>(p.kd, p.nt, p.kd == p.d, f);
   else if (p.fused) visit_fused<T>(p.dmax, f);
   else if (p.dmax) visit_tiled<T>(p.dmax, f);
   else r = resident_blocks(k_assign_generic<T>, 0, cus);
@@ -2953,14 +2956,15 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   // codes follow km_precision: 0 auto, 1 FP32, 2 BF16 screen)
   const bool screen = precision == 2 || (precision == 0 && dtype == 1 && d >= 32);
   const bool small = d <= 16 && k <= 128 &&
-                     kk * (size_t)p.dmax * 8 + kk * (dd + 1) * 8 <= budget;
+                     kk * (size_t)std::max(p.dmax, 2) * 8 + kk * (dd + 1) * 8 <= budget;
   p.bf16 = d <= 256 && screen && !small;
   if (p.bf16) {
     p.ks = d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 4 : d <= 128 ? 8 : 16;
     p.dmax = 0;
   }
-  // MFMA fused pass: d <= 32, k <= 128, LDS for FP64 centers + sums + counts
-  const size_t lds_mfma = kk * (dd + 1) * 8 * 2;
+  // fused MFMA passes (d <= 32, k <= 128): FP64 centers padded to the kernel's
+  // dims, and the sums with counts
+  const size_t lds_mfma = kk * (size_t)std::max(p.dmax, 2) * 8 + kk * (dd + 1) * 8;
   const size_t lds_fused = ((kk * (size_t)p.dmax + kk) * 4 + 15) / 16 * 16 + kk * (dd + 1) * 8;
   int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
   if (p.bf16) {
@@ -2976,12 +2980,13 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
     p.kd = p.dmax;
     p.d = d;
     p.nt = (k + 31) / 32;
-    p.lds_assign = kk * (size_t)p.kd * 8 + kk * (dd + 1) * 8;
+    p.lds_assign = kk * (size_t)std::max(p.dmax, 2) * 8 + kk * (dd + 1) * 8;
     work = ((rows + 31) / 32 + 3) / 4;
   } else if (d <= 32 && k <= 128 && lds_mfma <= budget) {
     p.mfma = true;
     p.fused = true;
     p.kd = p.dmax;
+    p.d = d;
     p.nt = (k + 31) / 32;
     p.lds_assign = lds_mfma;
     work = ((rows + 31) / 32 + 3) / 4;
@@ -3021,17 +3026,14 @@ static void dispatch_fused(const PassBufs& b, const PassPlan& p, bool update,
                        update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
   };
   if (p.fscreen) {
-    // the whole-row kernel loads half rows as aligned vectors
-    const size_t vb = (size_t)(p.kd / 2) * sizeof(T), al = vb < 16 ? vb : 16;
-    const bool full = p.kd == b.d && (reinterpret_cast<uintptr_t>(b.X) % al) == 0;
-    visit_fscreen<T>(p.kd, p.nt, full, [&](auto kern) {
+    visit_fscreen<T>(p.kd, p.nt, full_rows_ok<T>(p.kd, b.d, b.X), [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
                          (const T*)b.X, b.n, b.d, b.k, (const uint16_t*)b.cb16,
                          (const float*)b.cnB, (const double*)b.c64, (const PassState*)b.st,
                          gate, update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
     });
   } else if (p.mfma) {
-    visit_mfma<T>(p.kd, p.nt, launch);
+    visit_mfma<T>(p.kd, p.nt, full_rows_ok<T>(p.kd, b.d, b.X), launch);
   } else {
     visit_fused<T>(p.dmax, launch);
   }
