@@ -149,6 +149,7 @@ struct PassBufs {
 struct PassPlan {
   bool bf16;         // split pass with the BF16 MFMA screen (x.c^T as 32x32x16 tiles)
   bool fscreen;      // fused pass on the BF16 MFMA screen (d <= 16, k <= 128)
+  bool fsplit;       // ... with -2c and FP32 points as BF16 hi + lo parts (auto precision)
   int ks;            // 16-dim K steps of the BF16 screen
   bool mfma;         // fused pass on FP32 MFMA (x.c^T as 32x32x2 tiles)
   int kd, nt;        // padded dims and 32-center tiles of the MFMA kernels

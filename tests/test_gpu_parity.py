@@ -93,10 +93,10 @@ SMALL_D = [(1, 5), (2, 8), (4, 32), (5, 7), (8, 64), (16, 64), (16, 128), (3, 10
 
 
 @pytest.mark.parametrize("d,k", SMALL_D)
-@pytest.mark.parametrize("precision", ["bf16_rerank", "fp32"])
+@pytest.mark.parametrize("precision", ["auto", "bf16_rerank", "fp32"])
 def test_small_d_fused_paths(d, k, precision):
-    """d <= 16, k <= 128: the fused pass on the BF16 screen (precision
-    bf16_rerank) and on FP32 MFMA (fp32, also the auto choice) give the oracle's
+    """d <= 16, k <= 128: the fused pass on the split BF16 screen (auto), on the
+    plain BF16 screen (bf16_rerank) and on FP32 MFMA (fp32) give the oracle's
     labels, J and new centers."""
     n = 20_011
     print(f"[small-d {precision}] n={n} d={d} k={k}", flush=True)
@@ -386,6 +386,58 @@ def test_bf16_screen_band_covers_fp32_data_rounding(extra, d):
     assert (ref.labels == 1).all()
     print(f"[bf16 band f32] d={d} k={len(C)}", flush=True)
     lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="bf16_rerank")
+    assert (lab.cpu().numpy() == 1).all()
+    assert abs(J - ref.J) <= 1e-9 * ref.J
+
+
+@pytest.mark.parametrize("d", [16, 8, 4])
+@pytest.mark.parametrize("extra", [0, 38])
+@pytest.mark.parametrize("m", [128, 190, 255])
+def test_split_screen_band_covers_low_part_rounding(m, extra, d):
+    """Adversarial rounding of the centers' low BF16 parts (auto precision, small
+    d: the split screen).  x = (1, ..., 1) in BF16; -2c = -2 - 2t with 2t just
+    below (c1) or above (c2) a rounding midpoint of the low part, so the dropped
+    remainders e of the two centers are about -0.49 and +0.49 of the low part's
+    ulp in every dim: the screen prefers c2 by about d 2^-16 while c1 is
+    nearer (by far less)."""
+    u = 2.0 ** -15
+    t1, t2 = (m + 0.49) * u / 2, (m + 0.51) * u / 2
+    C = np.vstack([np.full((1, d), 1 + t1), np.full((1, d), 1 + t2), _far_centers(d, extra, m)])
+    Xh = synth_bf16(np.ones((64, d)))
+    ref = oracle.step(Xh, C)
+    assert (ref.labels == 0).all()
+    print(f"[split band c] d={d} m={m} k={len(C)}", flush=True)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="auto")
+    assert (lab.cpu().numpy() == 0).all()
+    assert abs(J - ref.J) <= 1e-9 * ref.J
+
+
+@pytest.mark.parametrize("d", [16, 8, 4])
+@pytest.mark.parametrize("extra", [0, 38])
+def test_split_screen_band_covers_fp32_low_part_rounding(extra, d):
+    """FP32 data whose low BF16 parts all round one way (auto precision, small d:
+    the split screen).  x_t = s_t (1 + rho_t) with signs s alternating, so
+    x^ = s; rho_t sits 2^-6 of an ulp (u = 2^-16) off a rounding midpoint of the
+    low part, so every dropped remainder is (1/2 - 2^-6) u against s_t.  With
+    c1 = -c2 = 0.5 (exact in BF16) the screen sees sum(x^ + xlo) > 0 (c1 nearer)
+    while sum(x) < 0 (c2 nearer)."""
+    u = 2.0 ** -16
+    half = d // 2
+    mp = np.full(half, 150)
+    mm = np.full(half, 150)
+    mm[: max(1, (31 * d) // 100)] += 1  # sum over s = -1 of m exceeds that over s = +1
+    # offsets 0.5 +- 2^-6 of an ulp: dyadic, so every x_t is exact in FP32
+    x = np.empty(d, np.float64)
+    x[0::2] = 1 + (mp + 0.5 + 2.0 ** -6) * u
+    x[1::2] = -(1 + (mm + 0.5 - 2.0 ** -6) * u)
+    xs = x.astype(np.float32)
+    assert np.array_equal(xs.astype(np.float64), x)
+    Xh = np.tile(xs, (64, 1))
+    C = np.vstack([np.full((1, d), 0.5), np.full((1, d), -0.5), _far_centers(d, extra, 3)])
+    ref = oracle.step(Xh, C)
+    assert x.sum() < 0 and (ref.labels == 1).all()
+    print(f"[split band f32] d={d} k={len(C)}", flush=True)
+    lab, J, _ = km.km_assign(to_device(Xh), torch.from_numpy(C).cuda(), precision="auto")
     assert (lab.cpu().numpy() == 1).all()
     assert abs(J - ref.J) <= 1e-9 * ref.J
 
