@@ -2030,6 +2030,357 @@ __global__ __launch_bounds__(256, (NT > 3 || (SPLIT && NT > 2)) ? 2 : 3) void k_
   block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
 }
 
+// Whole rows of X into registers: KD values of row `row` (zero past d).
+// FULL (d == KD): aligned vector loads (the launcher checks the alignment).
+template <typename T, int KD, bool FULL>
+__device__ __forceinline__ void load_row_full(const T* __restrict__ X, int64_t row, int d,
+                                              float (&xo)[KD]) {
+  if constexpr (FULL) {
+    const T* p = X + row * KD;
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int q = 0; q < KD; q += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p + q);
+        xo[q] = v.x; xo[q + 1] = v.y; xo[q + 2] = v.z; xo[q + 3] = v.w;
+      }
+    } else if constexpr (KD == 4) {
+      const uint2 w = *reinterpret_cast<const uint2*>(p);
+      xo[0] = bf16_lo(w.x); xo[1] = bf16_hi(w.x); xo[2] = bf16_lo(w.y); xo[3] = bf16_hi(w.y);
+    } else {
+#pragma unroll
+      for (int q = 0; q < KD; q += 8) {
+        const uint4 w = *reinterpret_cast<const uint4*>(p + q);
+        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xo[q + 2 * u] = bf16_lo(w4[u]);
+          xo[q + 2 * u + 1] = bf16_hi(w4[u]);
+        }
+      }
+    }
+  } else {
+    const T* p = X + row * d;
+#pragma unroll
+    for (int q = 0; q < KD; ++q) xo[q] = q < d ? widen<T>(p[q]) : 0.f;
+  }
+}
+
+// Whether the paired-tile kernel may load whole rows of X as aligned vectors.
+template <typename T>
+inline bool full_row_ok(int kd, int d, const void* X) {
+  const size_t rb = (size_t)kd * sizeof(T), al = rb < 16 ? rb : 16;
+  return kd == d && (reinterpret_cast<uintptr_t>(X) % al) == 0;
+}
+
+// FP64 check of the uncertain points of a wave whose lanes hold whole rows
+// (KD values, zero past d): for each such lane in turn the wave scores all
+// centers (lane j takes centers j, j + 64, ...; FP64 centers in LDS with row
+// stride KD), then reduces to the smallest distance, lowest index on ties.
+template <int KD>
+__device__ __forceinline__ int64_t row_fp64_check(bool unc, const float (&x)[KD], int k,
+                                                  const double* __restrict__ cs, int& label) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long m = __ballot(unc);
+  const int64_t cnt = __popcll(m);
+  while (m) {
+    const int src = __ffsll((long long)m) - 1;
+    m &= m - 1ull;
+    double xv[KD];
+#pragma unroll
+    for (int t = 0; t < KD; ++t)
+      xv[t] = (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[t]), src));
+    double bD = INFINITY;
+    int bj = INT_MAX;
+    for (int j = lane; j < k; j += 64) {
+      const double* cj = cs + (int64_t)j * KD;
+      double D = 0.0;
+#pragma unroll
+      for (int t = 0; t < KD; ++t) {
+        const double e = xv[t] - cj[t];
+        D = D + e * e;
+      }
+      if (D < bD) { bD = D; bj = j; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double oD = __shfl_xor(bD, o);
+      const int oj = __shfl_xor(bj, o);
+      if (oD < bD || (oD == bD && oj < bj)) { bD = oD; bj = oj; }
+    }
+    if (lane == src) label = bj < k ? bj : 0;
+  }
+  return cnt;
+}
+
+// The split screen's fused pass (auto precision, d <= 16, k <= 128) on pairs of
+// point tiles.  A wave takes 64 consecutive points; lane l loads the whole row
+// of point l and rounds it (x^, and xlo for FP32 data).  One permlane32 swap per
+// packed word gives each lane half the operand halves of both 32-point tiles
+// (tile A: points 0..31, tile B: points 32..63), so that every lane half holds
+// K elements 8h..8h+7 of both tiles' B operands, as the 32x32x16 MFMA wants.
+// Each lane ranks its 16 NT scores of both tiles (best three as keys, the lane
+// half in the index bits); one swap per key then hands lane l the other half's
+// keys of its own point (lane half 0 finishes tile A, half 1 tile B), so the
+// merge, the band, the FP64 decisions, J and the cluster sums run once per
+// point, on whole rows.  Scores, band and decisions as in the split screen of
+// the fused pass on single tiles.  FULL: d == KD.
+template <typename T, int KD, int NT, bool FULL>
+__global__ __launch_bounds__(256, 3) void k_fused_pair(
+    const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cnB,
+    const double* __restrict__ c64, const PassState* __restrict__ st,
+    const int32_t* __restrict__ gate, int update, long long* __restrict__ slots,
+    double* __restrict__ Jpart, long long* __restrict__ upart, int32_t* __restrict__ labels) {
+  if (gated(gate)) return;
+  constexpr int H = KD / 2;                              // dims per lane half
+  static_assert(KD >= 4 && KD <= 16, "whole packed words per lane half");
+  constexpr int HW = H / 2;                              // packed words per half row
+  constexpr int NS = sizeof(T) == 4 ? 3 : 2;             // products per dim
+  constexpr int NM = (NS * H + 7) / 8;                   // MFMAs per center tile
+  constexpr int NE = NM * 8;                             // K elements per lane half
+  constexpr int BL = NT == 1 ? 4 : (NT == 2 ? 5 : 6);   // bits of a lane-local index
+  constexpr int BG = BL + 1;                             // ... with the lane half
+  constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* cs = reinterpret_cast<double*>(smem);  // [k][KD] FP64 centers, zero past d
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * KD);  // [k][d+1]
+  // then, 16-byte aligned: the A operands [NT][NM][64 lanes] and the C input
+  // [32 NT] (both read from LDS where the MFMAs need them, which keeps the
+  // registers for two tiles of points)
+  const size_t tail = ((size_t)k * KD * 8 + (size_t)k * (d + 1) * 8 + 15) & ~(size_t)15;
+  v8bf* aop = reinterpret_cast<v8bf*>(smem + tail);
+  float* cbias = reinterpret_cast<float*>(smem + tail + (size_t)NT * NM * 64 * 16);
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int e = threadIdx.x; e < k * KD; e += 256) {
+    const int j = e / KD, t = e - j * KD;
+    cs[e] = t < d ? c64[(int64_t)j * d + t] : 0.0;
+  }
+  if (update)
+    for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
+  for (int e = threadIdx.x; e < 32 * NT; e += 256) cbias[e] = cnB[e];
+  __syncthreads();
+  // A operand of lane ln, center tile t: center row 32t + ln % 32, dims
+  // hH .. hH + H - 1 (h = ln / 32); K elements c'hi, c'lo and, for FP32 data,
+  // c'hi again, each over the half's H dims
+  for (int e = threadIdx.x; e < NT * 64; e += 256) {
+    const int t = e >> 6, ln = e & 63, hh = ln >> 5, j = 32 * t + (ln & 31);
+    uint16_t e16[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) e16[u] = 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      const double cp = j < k ? -2.0 * cs[j * KD + hh * H + q] : 0.0;
+      const uint16_t hi = f32_to_bf16((float)cp);
+      e16[q] = hi;
+      e16[H + q] = f32_to_bf16((float)(cp - (double)__uint_as_float((uint32_t)hi << 16)));
+      if constexpr (NS == 3) e16[2 * H + q] = hi;
+    }
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      u16x8 v;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = e16[8 * m + u];
+      aop[(t * NM + m) * 64 + ln] = __builtin_bit_cast(v8bf, v);
+    }
+  }
+  __syncthreads();
+  // The band of two scores, E2 = c0 + c1 xn + c2 xr (xn >= ||x^||, xr >= ||x - x^||):
+  // the dropped part x^.e + xlo.(c' - c'hi) + r.c' (||e|| <= 2^-8 ||c' - c'hi||,
+  // ||xlo|| <= (1 + 2^-8) ||x - x^||, ||r|| <= 2^-8 ||x - x^||) and the FP32
+  // accumulation of the C input and the products.
+  const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f, scale = st->scale;
+  const float ea = (float)(16 * NM + 8) * 0x1p-23f * 1.01f;
+  const float cc = 2.f * cmax + 2.004f * dcn;
+  const float c0 = (2.f * ea * (cmax * cmax + B) + 1e-30f) * 1.0001f;
+  const float c1 = (2.f * dcn * 0x1p-8f * 1.001f + 2.f * ea * cc) * 1.0001f;
+  const float c2 = (2.f * dcn * 1.004f + 0x1p-6f * cmax + 2.f * ea * 1.004f * cc) * 1.0001f;
+  const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
+  double Jacc = 0.0;
+  int64_t ucnt = 0, pcnt = 0;
+  const int64_t npair = (n + 63) >> 6;
+  const int64_t pstride = (int64_t)gridDim.x * 4;
+  int64_t pp = (int64_t)blockIdx.x * 4 + wave;
+  float xnext[KD];
+  // rows past n read the last row (their results are not used)
+  load_row_full<T, KD, FULL>(X, min((pp << 6) + lane, n - 1), d, xnext);
+  for (; pp < npair; pp += pstride) {
+    const int64_t i = (pp << 6) + lane;
+    const bool valid = i < n;
+    float x[KD];
+#pragma unroll
+    for (int q = 0; q < KD; ++q) x[q] = xnext[q];
+    load_row_full<T, KD, FULL>(X, min(((pp + pstride) << 6) + lane, n - 1), d, xnext);
+    // the row as BF16: x^ (RNE, two values per instruction) and, for FP32 data,
+    // xlo = BF16(x - x^) (the difference is exact); packed word w holds dims
+    // 2w, 2w + 1, so words [0, HW) are the first half row
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    uint32_t xw[H], lw[H] = {};
+    float s2 = 0.f, r2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      const f32x2 pr = {x[2 * q], x[2 * q + 1]};
+      xw[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(pr, bf16x2));
+      const float lo = bf16_lo(xw[q]), hi = bf16_hi(xw[q]);
+      s2 = __builtin_fmaf(lo, lo, s2);
+      s2 = __builtin_fmaf(hi, hi, s2);
+      if constexpr (sizeof(T) == 4) {
+        const f32x2 rr = {x[2 * q] - lo, x[2 * q + 1] - hi};
+        r2 = __builtin_fmaf(rr.x, rr.x, r2);
+        r2 = __builtin_fmaf(rr.y, rr.y, r2);
+        lw[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(rr, bf16x2));
+      }
+    }
+    // swap (first half word, second half word): afterwards word [0] is this
+    // lane half's part of tile A's point pc and [1] that of tile B's point pc
+    uint32_t hA[HW], hB[HW], lA[HW], lB[HW];
+#pragma unroll
+    for (int q = 0; q < HW; ++q) {
+      const auto r = __builtin_amdgcn_permlane32_swap(xw[q], xw[HW + q], false, false);
+      hA[q] = r[0];
+      hB[q] = r[1];
+      if constexpr (NS == 3) {
+        const auto s = __builtin_amdgcn_permlane32_swap(lw[q], lw[HW + q], false, false);
+        lA[q] = s[0];
+        lB[q] = s[1];
+      }
+    }
+    // B operands: the terms' words one after the other (x^, x^, then xlo for
+    // FP32 data), zero padded
+    auto operands = [&](const uint32_t (&hw)[HW], const uint32_t (&lo)[HW], v8bf (&ov)[NM]) {
+      uint32_t words[NE / 2];
+#pragma unroll
+      for (int w = 0; w < NE / 2; ++w) {
+        const int u = w / HW, q = w % HW;
+        words[w] = u < 2 ? hw[q] : (u == 2 && NS == 3 ? lo[q] : 0u);
+      }
+#pragma unroll
+      for (int m = 0; m < NM; ++m) {
+        const uint32_t w4[4] = {words[4 * m], words[4 * m + 1], words[4 * m + 2], words[4 * m + 3]};
+        ov[m] = __builtin_bit_cast(v8bf, w4);
+      }
+    };
+    v8bf oA[NM], oB[NM];
+    operands(hA, lA, oA);
+    operands(hB, lB, oB);
+    int a1 = INT_MAX, a2 = INT_MAX, a3 = INT_MAX, b1 = INT_MAX, b2 = INT_MAX, b3 = INT_MAX;
+    auto rank = [&](const v16f& acc, int t, int& m1, int& m2, int& m3) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        // the value part drops BG bits (the index bits and the lane half)
+        const int kv = (__float_as_int(acc[r]) & ~GM) | (16 * t + r);
+        m3 = med3_i32(m2, kv, m3);
+        m2 = med3_i32(m1, kv, m2);
+        m1 = min(m1, kv);
+      }
+    };
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      // the C input of this lane's rows 8(r/4) + 4h + r%4 of tile t
+      v16f bias;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 v = *reinterpret_cast<const float4*>(&cbias[32 * t + 8 * g + 4 * h]);
+        bias[4 * g] = v.x; bias[4 * g + 1] = v.y; bias[4 * g + 2] = v.z; bias[4 * g + 3] = v.w;
+      }
+      v8bf at = aop[(t * NM) * 64 + lane];
+      v16f accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at, oA[0], bias, 0, 0, 0);
+      v16f accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at, oB[0], bias, 0, 0, 0);
+#pragma unroll
+      for (int m = 1; m < NM; ++m) {
+        at = aop[(t * NM + m) * 64 + lane];
+        accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at, oA[m], accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(at, oB[m], accB, 0, 0, 0);
+      }
+      rank(accA, t, a1, a2, a3);
+      rank(accB, t, b1, b2, b3);
+    }
+    // the lane half into the index bits, then swap: lane l gets the other
+    // half's keys of its own point and merges
+    const int hb = h << BL;
+    int g1, g2, g3;
+    {
+      const auto s1 = __builtin_amdgcn_permlane32_swap(a1 | hb, b1 | hb, false, false);
+      const auto s2k = __builtin_amdgcn_permlane32_swap(a2 | hb, b2 | hb, false, false);
+      const auto s3 = __builtin_amdgcn_permlane32_swap(a3 | hb, b3 | hb, false, false);
+      g1 = (int)s1[0];
+      g2 = (int)s2k[0];
+      g3 = (int)s3[0];
+      const int ov[3] = {(int)s1[1], (int)s2k[1], (int)s3[1]};
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        g3 = med3_i32(g2, ov[u], g3);
+        g2 = med3_i32(g1, ov[u], g2);
+        g1 = min(g1, ov[u]);
+      }
+    }
+    // index bits -> center: local slot l of lane half hh is row
+    // 32 (l / 16) + 8 ((l % 16) / 4) + 4 hh + l % 4
+    auto center = [&](int key) {
+      const int l = key & LM, hh = (key >> BL) & 1;
+      return 32 * (l >> 4) + 8 * ((l & 15) >> 2) + 4 * hh + (l & 3);
+    };
+    int bi = center(g1);
+    const int bj2 = center(g2);
+    const float v1 = __int_as_float(g1 & ~GM), v2 = __int_as_float(g2 & ~GM),
+                v3 = __int_as_float(g3 & ~GM);
+    // norms for the band (the hardware square root is within an ulp; the 1%
+    // factor covers it)
+    const float xn = __builtin_amdgcn_sqrtf(s2) * 1.01f;
+    const float xr = sizeof(T) == 4 ? __builtin_amdgcn_sqrtf(r2) * 1.01f : 0.f;
+    const float E2 = __builtin_fmaf(c2, xr, __builtin_fmaf(c1, xn, c0));
+    auto apart = [&](float lo, float hi) {
+      return (hi - lo) > E2 + delta * (fabsf(hi) + fabsf(lo));
+    };
+    // certain: the best beats every other center; pair: the best is one of the best two
+    const bool certain = k == 1 || (bi < k && apart(v1, v2));
+    const bool pair = valid && !certain && bi < k && bj2 < k && (k == 2 || apart(v1, v3));
+    const bool full = valid && !certain && !pair;
+    if (bi >= k) bi = 0;
+    auto dist64 = [&](int j) {  // FP64 direct form over the whole row (zero past d)
+      const double* cj = cs + j * KD;
+      double p = 0.0;
+#pragma unroll
+      for (int q = 0; q < KD; ++q) {
+        const double e = (double)x[q] - cj[q];
+        p = __builtin_fma(e, e, p);
+      }
+      return p;
+    };
+    double p1 = dist64(bi);
+    if (__ballot(pair)) {
+      // the second candidate's FP64 distance decides (lowest index on ties)
+      const double p2 = dist64(pair ? bj2 : 0);
+      if (pair && (p2 < p1 || (p2 == p1 && bj2 < bi))) {
+        bi = bj2;
+        p1 = p2;
+      }
+      pcnt += __popcll(__ballot(pair));
+    }
+    if (__ballot(full)) {
+      ucnt += row_fp64_check<KD>(full, x, k, cs, bi);
+      if (full) p1 = dist64(bi);
+    }
+    if (valid) {
+      Jacc += p1;
+      if (labels) labels[i] = bi;
+      if (update) {
+        unsigned long long* Sr = S + (int64_t)bi * (d + 1);
+#pragma unroll
+        for (int q = 0; q < KD; ++q) {
+          if (FULL || q < d) {
+            const int qv = __float2int_rn(x[q] * scale);
+            atomicAdd(&Sr[q], (unsigned long long)(long long)qv);
+          }
+        }
+        atomicAdd(&Sr[d], 1ull);
+      }
+    }
+  }
+  __syncthreads();
+  if (update) flush_sums(S, k, d, slots);
+  block_sum_J(Jacc, ucnt, pcnt, Jpart, upart);
+}
+
 // The BF16 screen of all points.  A block (4 waves) takes 4*PT tiles of 32
 // points; each wave keeps its rows as the B operand of 32x32x16 BF16 MFMAs in
 // registers.  Centers stream through LDS in stages of 128 rows, double-buffered:
@@ -2936,6 +3287,25 @@ static void visit_fscreen(int kd, int nt, bool full, bool split, F&& f) {
   }
 }
 
+template <typename T, int KD, bool FULL, typename F>
+static void visit_pair_nt(int nt, F&& f) {
+  switch (nt) {
+    case 1: f(k_fused_pair<T, KD, 1, FULL>); break;
+    case 2: f(k_fused_pair<T, KD, 2, FULL>); break;
+    case 3: f(k_fused_pair<T, KD, 3, FULL>); break;
+    default: f(k_fused_pair<T, KD, 4, FULL>); break;
+  }
+}
+
+template <typename T, typename F>
+static void visit_pair(int kd, int nt, bool full, F&& f) {
+  switch (kd) {
+    case 4: full ? visit_pair_nt<T, 4, true>(nt, f) : visit_pair_nt<T, 4, false>(nt, f); break;
+    case 8: full ? visit_pair_nt<T, 8, true>(nt, f) : visit_pair_nt<T, 8, false>(nt, f); break;
+    default: full ? visit_pair_nt<T, 16, true>(nt, f) : visit_pair_nt<T, 16, false>(nt, f); break;
+  }
+}
+
 template <typename T, typename F>
 static void visit_fused(int dmax, F&& f) {
   switch (dmax) {
@@ -3004,7 +3374,8 @@ static int64_t plan_blocks(const PassPlan& p, int cus) {
   if (p.bf16)
     visit_screen<T>(p.ks,
                     [&](auto kern) { r = resident_blocks(kern, 0, cus, screen_threads(p.ks)); });
-  else if (p.fscreen) visit_fscreen<T>(p.kd, p.nt, p.kd == p.d, p.fsplit, f);
+  else if (p.fscreen && p.fsplit) visit_pair<T>(p.kd, p.nt, p.kd == p.d, f);
+  else if (p.fscreen) visit_fscreen<T>(p.kd, p.nt, p.kd == p.d, false, f);
   else if (p.mfma) visit_mfma<T>(p.kd, p.nt, p.kd == p.d, f);
   else if (p.fused) visit_fused<T>(p.dmax, f);
   else if (p.dmax) visit_tiled<T>(p.dmax, f);
@@ -3047,11 +3418,18 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
     p.fsplit = !screen;
     p.fused = true;
     p.ks = 1;
-    p.kd = p.dmax;
+    // the split screen runs on pairs of 32-point tiles, whole packed words per
+    // lane half (at least 4 dims)
+    p.kd = p.fsplit ? std::max(p.dmax, 4) : p.dmax;
     p.d = d;
     p.nt = (k + 31) / 32;
-    p.lds_assign = kk * (size_t)std::max(p.dmax, 2) * 8 + kk * (dd + 1) * 8;
-    work = ((rows + 31) / 32 + 3) / 4;
+    p.lds_assign = kk * (size_t)std::max(p.kd, 2) * 8 + kk * (dd + 1) * 8;
+    if (p.fsplit) {
+      // the paired-tile kernel also keeps its A operands and C input in LDS
+      const size_t nm = (size_t)((dtype == 0 ? 3 : 2) * (p.kd / 2) + 7) / 8;
+      p.lds_assign = (p.lds_assign + 15) / 16 * 16 + (size_t)p.nt * nm * 64 * 16 + (size_t)p.nt * 32 * 4;
+    }
+    work = p.fsplit ? ((rows + 63) / 64 + 3) / 4 : ((rows + 31) / 32 + 3) / 4;
   } else if (d <= 32 && k <= 128 && lds_mfma <= budget) {
     p.mfma = true;
     p.fused = true;
@@ -3095,8 +3473,15 @@ static void dispatch_fused(const PassBufs& b, const PassPlan& p, bool update,
                        b.n, b.d, b.k, b.cw, b.cn, b.c64, (const PassState*)b.st, gate,
                        update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
   };
-  if (p.fscreen) {
-    visit_fscreen<T>(p.kd, p.nt, full_rows_ok<T>(p.kd, b.d, b.X), p.fsplit, [&](auto kern) {
+  if (p.fscreen && p.fsplit) {
+    visit_pair<T>(p.kd, p.nt, full_row_ok<T>(p.kd, b.d, b.X), [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
+                         (const T*)b.X, b.n, b.d, b.k, (const float*)b.cnB,
+                         (const double*)b.c64, (const PassState*)b.st, gate, update ? 1 : 0,
+                         b.slots, b.Jpart, b.upart, b.labels);
+    });
+  } else if (p.fscreen) {
+    visit_fscreen<T>(p.kd, p.nt, full_rows_ok<T>(p.kd, b.d, b.X), false, [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
                          (const T*)b.X, b.n, b.d, b.k, (const float*)b.cnB, (const double*)b.c64, (const PassState*)b.st,
                          gate, update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
