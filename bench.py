@@ -241,9 +241,10 @@ def main() -> int:
     rows = prof["rows"][1] / max(1, launches)
     flops = 2.0 * rows * w.k * w.d
     algo_bytes = rows * w.d * (4 if w.dtype == "f32" else 2)
-    # the pass the library plans at auto precision: the split BF16 screen (BF16
-    # data, d >= 32) or the FP32 kernels
+    # the pass the library plans at auto precision: the BF16 screen (BF16 data,
+    # d >= 32), the fused split BF16 screen (d <= 16, k <= 128) or the FP32 kernels
     bf16_screen = w.dtype == "bf16" and w.d >= 32
+    split_screen = w.d <= 16 and w.k <= 128
     peak_flops = PEAK_BF16_TFLOPS if bf16_screen else PEAK_FP32_TFLOPS
     traffic = read_traffic(w.name)
     if algo_bytes / (PEAK_HBM_GBS * 1e9) > flops / (peak_flops * 1e12):
@@ -256,6 +257,10 @@ def main() -> int:
     if bf16_screen:
         kernel = ("slow-stage BF16 MFMA screen (slot-pair top-2 keys, certified candidates, "
                   "FP32/FP64 re-rank)")
+    elif split_screen:
+        kernel = ("slow-stage fused pass on the split BF16 screen (c'hi x^ + c'lo x^ + c'hi xlo "
+                  "on BF16 MFMA, FP32 accumulate, certified top-3 keys, FP64 decisions, J and "
+                  "exact cluster sums)")
     else:
         kernel = "slow-stage assignment kernel (fused assign + cluster sums)"
     roofline.update({
@@ -278,7 +283,9 @@ def main() -> int:
         "vs_baseline": None,
         # scores on BF16 MFMA (FP32 accumulation) for the screen, else FP32;
         # decisions certified in FP32/FP64
-        "dtype": "bf16" if bf16_screen else "f32",
+        # products in BF16 (the split screen: high and low BF16 parts), FP32
+        # accumulation; FP64 decisions near ties
+        "dtype": "bf16" if bf16_screen else ("bf16x3-split" if split_screen else "f32"),
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k,
                    "subset_frac": w.subset_frac, "max_iter": w.max_iter, "tol": w.tol,

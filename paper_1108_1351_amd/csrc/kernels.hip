@@ -1769,26 +1769,22 @@ __device__ __forceinline__ int opaque_vgpr(int v) {
 // being sunk past this point by the optimizer.
 __device__ __forceinline__ void pin_here(int& v) { asm volatile("" : "+v"(v)); }
 
-// Fused pass for d <= 16 and k <= 128 on the BF16 matrix cores.  A wave takes
-// 32 points at a time; lane half h holds dims [hH, hH + H) of its point (H = KD/2).
-// For each tile of 32 centers a chain of 32x32x16 BF16 MFMAs gives every lane 16
-// screened scores ||c||^2 + B + x.c' of its point (c' = -2c; lane and lane^32 hold
-// the two halves of the tile's centers; the C input is ||c||^2 + B).  The
-// products per dim: plain, c'hi x^ (c'hi the BF16 copy of c', x^ the point as
-// BF16); SPLIT, also c'lo x^ and (FP32 data) c'hi xlo, where c'lo = BF16(c' - c'hi)
-// and xlo = BF16(x - x^) carry the next 8 bits, so that the screen is about as
-// sharp as an FP32 one.  In lane half h the K elements list the terms one after
-// the other, each over the half's H dims; the point side repeats x^ (and adds
-// xlo), the center side pairs c'hi, c'lo, c'hi with them.  Each lane keeps its
-// best three as integer keys; the two halves' keys give the best three of all.
-// The screen's error band (the exact rounding-error norms of the center copy and
-// of the point, and the FP32 accumulation) certifies the best center; when only
-// the second best is within the band, FP64 distances decide between the two;
-// otherwise the FP64 check over all centers decides.  J in FP64 (each lane half
-// adds its dims' part) and the exact cluster sums as in the FP32 fused pass.
-// FULL: d == KD (no padded dims).
-template <typename T, int KD, int NT, bool FULL, bool SPLIT>
-__global__ __launch_bounds__(256, (NT > 3 || (SPLIT && NT > 2)) ? 2 : 3) void k_fused_screen(
+// Fused pass for d <= 16 and k <= 128 on the BF16 matrix cores (the BF16
+// screen asked for at small d).  A wave takes 32 points at a time; lane half h
+// holds dims [hH, hH + H) of its point (H = KD/2) as K elements 8h .. 8h + H - 1
+// of the MFMA operands (the others are zero).  For each tile of 32 centers one
+// 32x32x16 BF16 MFMA gives every lane 16 screened scores ||c||^2 + B + x^.c'hi
+// of its point (c'hi the BF16 copy of -2c, x^ the point as BF16; lane and
+// lane^32 hold the two halves of the tile's centers; the C input is
+// ||c||^2 + B).  Each lane keeps its best three as integer keys; the two halves'
+// keys give the best three of all.  The screen's error band (the exact
+// rounding-error norms of the center copy and of the point, and the FP32
+// accumulation) certifies the best center; when only the second best is within
+// the band, FP64 distances decide between the two; otherwise the FP64 check
+// over all centers decides.  J in FP64 (each lane half adds its dims' part) and
+// the exact cluster sums as in the FP32 fused pass.  FULL: d == KD.
+template <typename T, int KD, int NT, bool FULL>
+__global__ __launch_bounds__(256, NT > 3 ? 2 : 3) void k_fused_screen(
     const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cnB, const double* __restrict__ c64,
     const PassState* __restrict__ st, const int32_t* __restrict__ gate, int update,
     long long* __restrict__ slots, double* __restrict__ Jpart, long long* __restrict__ upart,
@@ -1796,10 +1792,6 @@ __global__ __launch_bounds__(256, (NT > 3 || (SPLIT && NT > 2)) ? 2 : 3) void k_
   if (gated(gate)) return;
   constexpr int H = KD / 2;                             // dims per lane half
   static_assert(KD >= 2 && KD <= 16, "one 16-element K step holds both halves");
-  // products per dim and MFMAs per center tile (8 K elements per lane each)
-  constexpr int NS = !SPLIT ? 1 : (sizeof(T) == 4 ? 3 : 2);
-  constexpr int NM = (NS * H + 7) / 8;
-  constexpr int NE = NM * 8;                            // K elements per lane, zero padded
   constexpr int BL = NT == 1 ? 4 : (NT == 2 ? 5 : 6);  // bits of a lane-local index (16*NT values)
   constexpr int BG = BL + 1;                            // bits of a center index (32*NT centers)
   constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
@@ -1814,42 +1806,24 @@ __global__ __launch_bounds__(256, (NT > 3 || (SPLIT && NT > 2)) ? 2 : 3) void k_
   if (update)
     for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
   __syncthreads();
-  // A operands (center rows 32t + pc, dims hH .. hH + H - 1) and the C input
-  // (rows 8(r/4) + 4h + r%4 of the tile) of every center tile.  c'hi is the
-  // rounding the center copy holds (its error norm is the one the pass state
-  // keeps); with SPLIT, c'lo is the BF16 of the exact remainder.
-  v8bf a[NT][NM];
+  // A operand (center rows 32t + pc, dims hH .. hH + H - 1 of the BF16 copy of
+  // -2c, rounded as the pass state's error norm assumes) and the C input (rows
+  // 8(r/4) + 4h + r%4 of the tile) of every center tile
+  v8bf a[NT];
   v16f bias[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int j = 32 * t + pc;
-    uint16_t e16[NE];
+    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int e = 0; e < NE; ++e) e16[e] = 0;
-#pragma unroll
-    for (int q = 0; q < H; ++q) {
-      const double cp = j < k ? -2.0 * cs[j * KD + h * H + q] : 0.0;
-      const uint16_t hi = f32_to_bf16((float)cp);
-      e16[q] = hi;
-      if constexpr (SPLIT) {
-        const uint16_t lo = f32_to_bf16((float)(cp - (double)__uint_as_float((uint32_t)hi << 16)));
-        e16[H + q] = lo;
-        if constexpr (NS == 3) e16[2 * H + q] = hi;
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < NM; ++m) {
-      u16x8 v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = e16[8 * m + e];
-      a[t][m] = __builtin_bit_cast(v8bf, v);
-    }
+    for (int q = 0; q < H; ++q)
+      v[q] = f32_to_bf16((float)(j < k ? -2.0 * cs[j * KD + h * H + q] : 0.0));
+    a[t] = __builtin_bit_cast(v8bf, v);
 #pragma unroll
     for (int r = 0; r < 16; ++r) bias[t][r] = cnB[32 * t + 8 * (r >> 2) + 4 * h + (r & 3)];
   }
   const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f, scale = st->scale;
-  // FP32 accumulation over the chain's 16 NM products and the C input
-  const float ea = (float)(16 * NM + 8) * 0x1p-23f * 1.01f;
+  const float ea = (float)(16 + 8) * 0x1p-23f * 1.01f;
   const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
   auto load_x = [&](int64_t row, float (&xo)[H]) { load_half_row<T, KD, FULL>(X, row, d, h, xo); };
   double Jacc = 0.0;
@@ -1868,13 +1842,12 @@ __global__ __launch_bounds__(256, (NT > 3 || (SPLIT && NT > 2)) ? 2 : 3) void k_
     for (int q = 0; q < H; ++q) x[q] = xnext[q];
     // rows of this wave's next tile, loaded while this one computes
     load_x(min(((tile + tstride) << 5) + pc, n - 1), xnext);
-    // the point's BF16 elements: x^ (BF16 data as is; FP32 data rounded to
-    // nearest even, two values per instruction) and, with SPLIT and FP32 data,
-    // xlo = BF16(x - x^) (the difference is exact in FP32)
+    // the point as the B operand (BF16 data is exact; FP32 data rounds to
+    // nearest even, two values per instruction)
     typedef float f32x2 __attribute__((ext_vector_type(2)));
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     constexpr int HP = (H + 1) / 2;  // packed pairs
-    uint32_t xw[HP], lw[HP] = {};
+    uint32_t xw[4] = {0u, 0u, 0u, 0u};
     float s2 = 0.f, r2 = 0.f;
 #pragma unroll
     for (int q = 0; q < HP; ++q) {
@@ -1884,51 +1857,24 @@ __global__ __launch_bounds__(256, (NT > 3 || (SPLIT && NT > 2)) ? 2 : 3) void k_
       s2 = __builtin_fmaf(lo, lo, s2);
       s2 = __builtin_fmaf(hi, hi, s2);
       if constexpr (sizeof(T) == 4) {
-        const f32x2 rr = {x[2 * q] - lo, 2 * q + 1 < H ? x[2 * q + 1] - hi : 0.f};  // exact
-        r2 = __builtin_fmaf(rr.x, rr.x, r2);
-        r2 = __builtin_fmaf(rr.y, rr.y, r2);
-        if constexpr (SPLIT) lw[q] = __builtin_bit_cast(uint32_t, __builtin_convertvector(rr, bf16x2));
+        const float r0 = x[2 * q] - lo;  // exact
+        r2 = __builtin_fmaf(r0, r0, r2);
+        if (2 * q + 1 < H) {
+          const float r1 = x[2 * q + 1] - hi;
+          r2 = __builtin_fmaf(r1, r1, r2);
+        }
       }
     }
     // norms for the band (the hardware square root is within an ulp; the 1%
-    // factor covers it): xn >= ||x^||, xr >= ||x - x^||
+    // factor covers it)
     const float xn = __builtin_amdgcn_sqrtf(sum_halves(s2, h)) * 1.01f;
     float xr = 0.f;
     if constexpr (sizeof(T) == 4) xr = __builtin_amdgcn_sqrtf(sum_halves(r2, h)) * 1.01f;
-    // B operands: the terms' elements one after the other (x^; with SPLIT x^
-    // again, then xlo for FP32 data), zero padded
-    v8bf xv[NM];
-    {
-      auto elem = [&](const uint32_t (&w)[HP], int q) -> uint32_t {
-        return (q & 1) ? (w[q >> 1] >> 16) : (w[q >> 1] & 0xffffu);
-      };
-      uint32_t words[NE / 2];
-#pragma unroll
-      for (int w = 0; w < NE / 2; ++w) {
-        uint32_t v = 0u;
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-          const int e = 2 * w + half, u = e / H, q = e % H;
-          uint32_t b = 0u;
-          if (u == 0 || (u == 1 && NS >= 2)) b = elem(xw, q);
-          else if (u == 2 && NS == 3) b = elem(lw, q);
-          v |= b << (16 * half);
-        }
-        words[w] = v;
-      }
-#pragma unroll
-      for (int m = 0; m < NM; ++m) {
-        const uint32_t w4[4] = {words[4 * m], words[4 * m + 1], words[4 * m + 2], words[4 * m + 3]};
-        xv[m] = __builtin_bit_cast(v8bf, w4);
-      }
-    }
+    const v8bf xv = __builtin_bit_cast(v8bf, xw);
     int m1 = INT_MAX, m2 = INT_MAX, m3 = INT_MAX;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      v16f acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t][0], xv[0], bias[t], 0, 0, 0);
-#pragma unroll
-      for (int m = 1; m < NM; ++m)
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t][m], xv[m], acc, 0, 0, 0);
+      const v16f acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t], xv, bias[t], 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         // the value part drops BG bits already here, so that the switch to the
@@ -1957,19 +1903,10 @@ __global__ __launch_bounds__(256, (NT > 3 || (SPLIT && NT > 2)) ? 2 : 3) void k_
     const int b2 = g2 & GM;
     const float v1 = __int_as_float(g1 & ~GM), v2 = __int_as_float(g2 & ~GM),
                 v3 = __int_as_float(g3 & ~GM);
-    // Two screened scores differ from their exact values by at most E2 together.
-    // Plain: x.c' - x^.c'hi = x^.(c' - c'hi) + (x - x^).c'.  SPLIT: with
-    // c' = c'hi + c'lo + e and x = x^ + xlo + r, the dropped part is
-    // x^.e + xlo.(c' - c'hi) + r.c', where ||e|| <= 2^-8 ||c' - c'hi||,
-    // ||xlo|| <= (1 + 2^-8) ||x - x^|| and ||r|| <= 2^-8 ||x - x^||.  Then the
-    // FP32 accumulation of the C input and the products.
-    float E2;
-    if constexpr (!SPLIT)
-      E2 = 2.f * xn * dcn + 4.f * xr * cmax + 2.f * ea * (cmax * cmax + B + 2.f * xn * cmax);
-    else
-      E2 = 2.f * dcn * (0x1p-8f * 1.001f * xn + 1.004f * xr) + 0x1p-6f * xr * cmax +
-           2.f * ea * (cmax * cmax + B + (xn + 1.004f * xr) * (2.f * cmax + 2.004f * dcn)) +
-           1e-30f;
+    // two screened scores differ from their exact values by at most E2 together
+    // (x.c' - x^.c'hi = x^.(c' - c'hi) + (x - x^).c', and the FP32 accumulation)
+    const float E2 = 2.f * xn * dcn + 4.f * xr * cmax +
+                     2.f * ea * (cmax * cmax + B + 2.f * xn * cmax);
     auto apart = [&](float lo, float hi) {
       return (hi - lo) > E2 + delta * (fabsf(hi) + fabsf(lo));
     };
@@ -2111,18 +2048,24 @@ __device__ __forceinline__ int64_t row_fp64_check(bool unc, const float (&x)[KD]
   return cnt;
 }
 
-// The split screen's fused pass (auto precision, d <= 16, k <= 128) on pairs of
-// point tiles.  A wave takes 64 consecutive points; lane l loads the whole row
-// of point l and rounds it (x^, and xlo for FP32 data).  One permlane32 swap per
-// packed word gives each lane half the operand halves of both 32-point tiles
-// (tile A: points 0..31, tile B: points 32..63), so that every lane half holds
-// K elements 8h..8h+7 of both tiles' B operands, as the 32x32x16 MFMA wants.
-// Each lane ranks its 16 NT scores of both tiles (best three as keys, the lane
-// half in the index bits); one swap per key then hands lane l the other half's
-// keys of its own point (lane half 0 finishes tile A, half 1 tile B), so the
-// merge, the band, the FP64 decisions, J and the cluster sums run once per
-// point, on whole rows.  Scores, band and decisions as in the split screen of
-// the fused pass on single tiles.  FULL: d == KD.
+// The fused pass of auto precision for d <= 16 and k <= 128: a split BF16
+// screen on pairs of point tiles.  Scores ||c||^2 + B + x.c' (c' = -2c) come from
+// 32x32x16 BF16 MFMAs with FP32 accumulation (C input ||c||^2 + B) over three
+// products per dim, c'hi x^ + c'lo x^ + c'hi xlo, where c'hi and x^ are the BF16
+// roundings, c'lo = BF16(c' - c'hi) and xlo = BF16(x - x^) carry the next 8 bits
+// (BF16 data: x^ = x, two products).  In lane half h the K elements list the
+// terms one after the other, each over the half's H dims.
+// A wave takes 64 consecutive points; lane l loads the whole row of point l and
+// rounds it.  One permlane32 swap per packed word gives each lane half its
+// operand halves of both 32-point tiles (tile A: points 0..31, tile B: 32..63).
+// Each lane ranks its 16 NT scores of both tiles (best three as integer keys,
+// score bits with the slot and the lane half in the low bits); one swap per key
+// then hands lane l the other half's keys of its own point (lane half 0
+// finishes tile A, half 1 tile B), so the merge, the error band, the FP64
+// decisions, J and the cluster sums run once per point, on whole rows.  The
+// band certifies the best center; when only the second best is within it, FP64
+// distances decide between the two; otherwise the FP64 check over all centers
+// decides.  FULL: d == KD.
 template <typename T, int KD, int NT, bool FULL>
 __global__ __launch_bounds__(256, 3) void k_fused_pair(
     const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cnB,
@@ -3257,33 +3200,23 @@ static void visit_mfma(int kd, int nt, bool full, F&& f) {
   }
 }
 
-template <typename T, int KD, bool FULL, bool SPLIT, typename F>
+template <typename T, int KD, bool FULL, typename F>
 static void visit_fscreen_nt(int nt, F&& f) {
   switch (nt) {
-    case 1: f(k_fused_screen<T, KD, 1, FULL, SPLIT>); break;
-    case 2: f(k_fused_screen<T, KD, 2, FULL, SPLIT>); break;
-    case 3: f(k_fused_screen<T, KD, 3, FULL, SPLIT>); break;
-    default: f(k_fused_screen<T, KD, 4, FULL, SPLIT>); break;
-  }
-}
-
-template <typename T, int KD, typename F>
-static void visit_fscreen_kd(int nt, bool full, bool split, F&& f) {
-  if (split) {
-    full ? visit_fscreen_nt<T, KD, true, true>(nt, f) : visit_fscreen_nt<T, KD, false, true>(nt, f);
-  } else {
-    full ? visit_fscreen_nt<T, KD, true, false>(nt, f)
-         : visit_fscreen_nt<T, KD, false, false>(nt, f);
+    case 1: f(k_fused_screen<T, KD, 1, FULL>); break;
+    case 2: f(k_fused_screen<T, KD, 2, FULL>); break;
+    case 3: f(k_fused_screen<T, KD, 3, FULL>); break;
+    default: f(k_fused_screen<T, KD, 4, FULL>); break;
   }
 }
 
 template <typename T, typename F>
-static void visit_fscreen(int kd, int nt, bool full, bool split, F&& f) {
+static void visit_fscreen(int kd, int nt, bool full, F&& f) {
   switch (kd) {
-    case 2: visit_fscreen_kd<T, 2>(nt, full, split, f); break;
-    case 4: visit_fscreen_kd<T, 4>(nt, full, split, f); break;
-    case 8: visit_fscreen_kd<T, 8>(nt, full, split, f); break;
-    default: visit_fscreen_kd<T, 16>(nt, full, split, f); break;
+    case 2: full ? visit_fscreen_nt<T, 2, true>(nt, f) : visit_fscreen_nt<T, 2, false>(nt, f); break;
+    case 4: full ? visit_fscreen_nt<T, 4, true>(nt, f) : visit_fscreen_nt<T, 4, false>(nt, f); break;
+    case 8: full ? visit_fscreen_nt<T, 8, true>(nt, f) : visit_fscreen_nt<T, 8, false>(nt, f); break;
+    default: full ? visit_fscreen_nt<T, 16, true>(nt, f) : visit_fscreen_nt<T, 16, false>(nt, f); break;
   }
 }
 
@@ -3375,7 +3308,7 @@ static int64_t plan_blocks(const PassPlan& p, int cus) {
     visit_screen<T>(p.ks,
                     [&](auto kern) { r = resident_blocks(kern, 0, cus, screen_threads(p.ks)); });
   else if (p.fscreen && p.fsplit) visit_pair<T>(p.kd, p.nt, p.kd == p.d, f);
-  else if (p.fscreen) visit_fscreen<T>(p.kd, p.nt, p.kd == p.d, false, f);
+  else if (p.fscreen) visit_fscreen<T>(p.kd, p.nt, p.kd == p.d, f);
   else if (p.mfma) visit_mfma<T>(p.kd, p.nt, p.kd == p.d, f);
   else if (p.fused) visit_fused<T>(p.dmax, f);
   else if (p.dmax) visit_tiled<T>(p.dmax, f);
@@ -3481,7 +3414,7 @@ static void dispatch_fused(const PassBufs& b, const PassPlan& p, bool update,
                          b.slots, b.Jpart, b.upart, b.labels);
     });
   } else if (p.fscreen) {
-    visit_fscreen<T>(p.kd, p.nt, full_rows_ok<T>(p.kd, b.d, b.X), false, [&](auto kern) {
+    visit_fscreen<T>(p.kd, p.nt, full_rows_ok<T>(p.kd, b.d, b.X), [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(256), p.lds_assign, s,
                          (const T*)b.X, b.n, b.d, b.k, (const float*)b.cnB, (const double*)b.c64, (const PassState*)b.st,
                          gate, update ? 1 : 0, b.slots, b.Jpart, b.upart, b.labels);
