@@ -59,7 +59,10 @@ typedef enum {
 typedef enum { KM_F32 = 0, KM_BF16 = 1 } km_dtype;
 
 typedef enum {
-  KM_PREC_AUTO = 0,        /* FP32 for FP32 data, BF16 MFMA + re-rank for BF16 data with d >= 32 */
+  KM_PREC_AUTO = 0,        /* d <= 16 and k <= 128: split BF16 MFMA screen (-2c and FP32 points as
+                              BF16 high + low parts, FP32 accumulation); BF16 data with d >= 32:
+                              BF16 MFMA + re-rank; otherwise FP32.  Every screen is certified:
+                              points its error band cannot decide get FP64 decisions */
   KM_PREC_FP32 = 1,        /* FP32 distances, FP64 check of uncertain points */
   KM_PREC_BF16_RERANK = 2  /* BF16 MFMA x.c^T, FP32 re-rank of the top 4, FP64 check */
 } km_precision;
