@@ -2130,7 +2130,8 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
   // the dropped part x^.e + xlo.(c' - c'hi) + r.c' (||e|| <= 2^-8 ||c' - c'hi||,
   // ||xlo|| <= (1 + 2^-8) ||x - x^||, ||r|| <= 2^-8 ||x - x^||) and the FP32
   // accumulation of the C input and the products.
-  const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f, scale = st->scale;
+  const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f;
+  const double scale64 = (double)st->scale;
   const float ea = (float)(16 * NM + 8) * 0x1p-23f * 1.01f;
   const float cc = 2.f * cmax + 2.004f * dcn;
   const float c0 = (2.f * ea * (cmax * cmax + B) + 1e-30f) * 1.0001f;
@@ -2279,12 +2280,15 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
     const bool pair = valid && !certain && bi < k && bj2 < k && (k == 2 || apart(v1, v3));
     const bool full = valid && !certain && !pair;
     if (bi >= k) bi = 0;
+    double x64[KD];
+#pragma unroll
+    for (int q = 0; q < KD; ++q) x64[q] = (double)x[q];
     auto dist64 = [&](int j) {  // FP64 direct form over the whole row (zero past d)
       const double* cj = cs + j * KD;
       double p = 0.0;
 #pragma unroll
       for (int q = 0; q < KD; ++q) {
-        const double e = (double)x[q] - cj[q];
+        const double e = x64[q] - cj[q];
         p = __builtin_fma(e, e, p);
       }
       return p;
@@ -2307,12 +2311,14 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
       Jacc += p1;
       if (labels) labels[i] = bi;
       if (update) {
+        // q = rint(x 2^F) as the bits of 1.5 2^52 + q: one FMA (x 2^F is exact,
+        // |q| < 2^30), added biased; the finalize takes N kSumBias off
         unsigned long long* Sr = S + (int64_t)bi * (d + 1);
 #pragma unroll
         for (int q = 0; q < KD; ++q) {
           if (FULL || q < d) {
-            const int qv = __float2int_rn(x[q] * scale);
-            atomicAdd(&Sr[q], (unsigned long long)(long long)qv);
+            const double tq = __builtin_fma(x64[q], scale64, 0x1.8p52);
+            atomicAdd(&Sr[q], (unsigned long long)__double_as_longlong(tq));
           }
         }
         atomicAdd(&Sr[d], 1ull);
@@ -2880,17 +2886,20 @@ __device__ void finalize_center(
     int32_t* __restrict__ emptyj, double* __restrict__ S_out, int64_t* __restrict__ N_out,
     uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
-    double* __restrict__ J_hist, double* __restrict__ shift_hist, bool mark_labelled = false) {
+    double* __restrict__ J_hist, double* __restrict__ shift_hist, bool mark_labelled = false,
+    bool biased = false) {
   const int tid = threadIdx.x;
   const int64_t C = (int64_t)k * (d + 1);
   long long* col = slots + (int64_t)j * (d + 1);
   __shared__ long long red[256];
+  __shared__ long long scnt[kSlots];  // points per slot row (biased sums)
   __shared__ double rd[256], rn[256], re[256];
   __shared__ int last;
   long long v = 0;
   if (tid < kSlots) {
     v = col[(int64_t)tid * C + d];
     col[(int64_t)tid * C + d] = 0;
+    scnt[tid] = v;
   }
   red[tid] = v;
   __syncthreads();
@@ -2909,6 +2918,9 @@ __device__ void finalize_center(
     if (t < d) {
       sv = col[(int64_t)r * C + t];
       col[(int64_t)r * C + t] = 0;
+      // biased sums: every point added kSumBias + q (mod 2^64)
+      if (biased)
+        sv = (long long)((unsigned long long)sv - (unsigned long long)scnt[r] * kSumBias);
     }
     red[tid] = sv;
     __syncthreads();
@@ -2984,10 +2996,11 @@ __global__ __launch_bounds__(256) void k_finalize(
     double* __restrict__ S_out, int64_t* __restrict__ N_out,
     uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
-    double* __restrict__ J_hist, double* __restrict__ shift_hist) {
+    double* __restrict__ J_hist, double* __restrict__ shift_hist, int biased) {
   if (gated(gate)) return;
   finalize_center(blockIdx.x, slots, jslots, k, d, st, update, c64, cw, cn, cnorm, shiftj, emptyj,
-                  S_out, N_out, cb16, cnB, kd16, Jpart, upart, nb, J_hist, shift_hist);
+                  S_out, N_out, cb16, cnB, kd16, Jpart, upart, nb, J_hist, shift_hist, false,
+                  biased != 0);
 }
 
 // J and FP64-check counts of a labelling pass of the fused paths.  One block.
@@ -3542,7 +3555,7 @@ hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStrea
                        b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out,
                        copy16(p) ? b.cb16 : nullptr, copy16(p) ? b.cnB : nullptr, p.ks * 16,
                        (const double*)b.Jpart, (const long long*)b.upart, nb, b.J_hist,
-                       b.shift_hist);
+                       b.shift_hist, (p.fscreen && p.fsplit) ? 1 : 0);
   } else {
     hipLaunchKernelGGL(k_sum_J, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
                        (const long long*)b.upart, nb);

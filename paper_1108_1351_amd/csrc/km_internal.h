@@ -11,6 +11,9 @@ constexpr int kSelBins = 1 << kSelDigitBits;
 constexpr int64_t kSelChunk = 8192;   // indices per block in the ordered compaction
 constexpr int kThreads = 256;          // threads per block of the point kernels
 constexpr int kSlots = 32;             // rows of 64-bit cluster-sum slots blocks add into
+// Bias of the sums of the paired-tile pass: each term is added as the bits of
+// 1.5 2^52 + q (q = rint(x 2^F)), so the finalize subtracts N of these (mod 2^64).
+constexpr unsigned long long kSumBias = 0x4338000000000000ull;
 constexpr int kMaxBlocks = 4096;       // upper bound of an assignment kernel's grid
 constexpr int kHistLds = 16384;        // labels up to this count are sorted with LDS counters
 constexpr int kScreenRows = 256;       // BF16 center rows are padded to a multiple of this
