@@ -2362,7 +2362,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
   __shared__ __align__(16) uint16_t cb0[SC * KD], cb1[SC * KD];
   __shared__ __align__(16) float bb0[SC], bb1[SC];
   __shared__ int cand_j[64 * NW * 4];
-  __shared__ float pf_sink[64];  // lands the L2 prefetch touches below (never read)
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31;
   // wave-uniform (scalar) wave index: the stage-copy loops below then run on
   // the scalar unit
@@ -2402,25 +2401,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
       __builtin_amdgcn_global_load_lds(
           static_cast<const void*>(cnB + (int64_t)g * SC + 64 * i + lane),
           static_cast<void*>(bdst + 64 * i), 4, 0, 0);
-  };
-  // The first 16 KB of the rows this wave takes in the batch starting at
-  // `nbase`, brought into L2 ahead of their loads: one 4-byte LDS-direct copy
-  // per 128-byte line (the data lands in pf_sink and is never read).  The
-  // copies complete by the next stage barrier.
-  const int64_t xbytes = n * (int64_t)d * (int64_t)sizeof(T);
-  const bool x_aligned = (reinterpret_cast<uintptr_t>(X) & 3u) == 0;
-  auto prefetch_rows = [&](int64_t nbase) {
-    if (nbase >= n || !x_aligned) return;
-    const int64_t b0 = (nbase + (int64_t)wave * PT * 32) * (int64_t)d * (int64_t)sizeof(T);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      // a 4-byte aligned word that lies inside X
-      const int64_t off = (b0 + ((int64_t)i * 64 + lane) * 128) & ~(int64_t)3;
-      const int64_t at = off + 4 <= xbytes ? off : 0;
-      __builtin_amdgcn_global_load_lds(
-          static_cast<const void*>(reinterpret_cast<const char*>(X) + at),
-          static_cast<void*>(pf_sink), 4, 0, 0);
-    }
   };
   // every wave's LDS-direct loads are in LDS before the barrier
   auto stage_sync = [&]() {
@@ -2553,7 +2533,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
       compute_stage(gs, cb0, bb0);
       stage_sync();
       if (g + 2 < nst) issue_stage(gs2, cb0, bb0);
-      else prefetch_rows(base + (int64_t)gridDim.x * per_block);
       compute_stage(gs1, cb1, bb1);
       stage_sync();
       gs = gs2;
@@ -2804,6 +2783,21 @@ __global__ __launch_bounds__(512) void k_rescreen_bf16(
 // update's exact limbs in jslots, which are zeroed for the next pass), of the
 // FP64 check counts, and (when update) the largest movement, the largest ||c|| and
 // the empties; then the pass bookkeeping.
+// Sum or maximum over the 64 lanes of a wave by an xor butterfly: every lane
+// gets the same bits (each step adds the same two partials, in either order).
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ long long wave_sum(long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
 __device__ void conclude_block(PassState* __restrict__ st, const double* __restrict__ Jpart,
                                const long long* __restrict__ upart, int64_t nb,
                                long long* __restrict__ jslots, const double* __restrict__ shiftj,
@@ -2811,9 +2805,9 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
                                const int32_t* __restrict__ emptyj, int k, bool update,
                                double* __restrict__ J_hist, double* __restrict__ shift_hist,
                                bool mark_labelled = false) {
-  __shared__ double rJ[256], rS[256], rN[256];
-  __shared__ long long rU[256], rE[256], rP[256];
-  const int tid = threadIdx.x;
+  __shared__ double wJ[4], wS[4], wN[4];
+  __shared__ long long wU[4], wE[4], wP[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double J = 0.0, sh = 0.0, nm = 0.0;
   long long U = 0, E = 0, Pc = 0;
   for (int64_t b = tid; b < nb; b += 256) {
@@ -2827,20 +2821,20 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
       nm = fmax(nm, ld_agent(&cnorm[j]));
       E += ld_agent(&emptyj[j]);
     }
-  rJ[tid] = J; rU[tid] = U; rS[tid] = sh; rN[tid] = nm; rE[tid] = E; rP[tid] = Pc;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) {
-      rJ[tid] += rJ[tid + o];
-      rU[tid] += rU[tid + o];
-      rP[tid] += rP[tid + o];
-      rS[tid] = fmax(rS[tid], rS[tid + o]);
-      rN[tid] = fmax(rN[tid], rN[tid + o]);
-      rE[tid] += rE[tid + o];
-    }
-    __syncthreads();
+  // fixed-order reductions: lanes of a wave, then the four waves
+  J = wave_sum(J); U = wave_sum(U); Pc = wave_sum(Pc); E = wave_sum(E);
+  sh = wave_max(sh); nm = wave_max(nm);
+  if (lane == 0) {
+    wJ[wv] = J; wU[wv] = U; wP[wv] = Pc; wE[wv] = E; wS[wv] = sh; wN[wv] = nm;
   }
+  __syncthreads();
   if (tid == 0) {
+    double Jt = (wJ[0] + wJ[1]) + (wJ[2] + wJ[3]);
+    const long long Ut = (wU[0] + wU[1]) + (wU[2] + wU[3]);
+    const long long Pt = (wP[0] + wP[1]) + (wP[2] + wP[3]);
+    const long long Et = (wE[0] + wE[1]) + (wE[2] + wE[3]);
+    const double St = fmax(fmax(wS[0], wS[1]), fmax(wS[2], wS[3]));
+    const double Nt = fmax(fmax(wN[0], wN[1]), fmax(wN[2], wN[3]));
     if (jslots) {
       // the sorted update's J: exact integer limbs of 2^-FJ and 2^(40-FJ)
       long long a0 = 0, a1 = 0;
@@ -2852,21 +2846,21 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
       }
       a1 += a0 >> 40;
       a0 &= (1ll << 40) - 1;
-      rJ[0] = ldexp((double)a1, 40 - st->FJ) + ldexp((double)a0, -st->FJ);
+      Jt = ldexp((double)a1, 40 - st->FJ) + ldexp((double)a0, -st->FJ);
     }
-    st->J = rJ[0];
-    st->uncertain += rU[0];
-    st->pairs += rP[0];
+    st->J = Jt;
+    st->uncertain += Ut;
+    st->pairs += Pt;
     st->qcount = 0u;
     if (update) {
       const int it = st->iter;
-      st->shift = rS[0];
-      st->empty = (int32_t)rE[0];
-      st->cmax = (float)(rN[0] * (1.0 + 0x1p-20)) * (1.0f + 0x1p-20f);
-      if (J_hist) J_hist[it] = rJ[0];
-      if (shift_hist) shift_hist[it] = rS[0];
+      st->shift = St;
+      st->empty = (int32_t)Et;
+      st->cmax = (float)(Nt * (1.0 + 0x1p-20)) * (1.0f + 0x1p-20f);
+      if (J_hist) J_hist[it] = Jt;
+      if (shift_hist) shift_hist[it] = St;
       st->iter = it + 1;
-      st->converged = rS[0] < st->tol ? 1 : 0;
+      st->converged = St < st->tol ? 1 : 0;
       st->done = (st->converged || it + 1 >= st->max_iter) ? 1 : 0;
     } else if (mark_labelled) {
       st->done = 2;  // a batched labelling pass ran; later launches skip it
@@ -2888,27 +2882,25 @@ __device__ void finalize_center(
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
     double* __restrict__ J_hist, double* __restrict__ shift_hist, bool mark_labelled = false,
     bool biased = false) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t C = (int64_t)k * (d + 1);
   long long* col = slots + (int64_t)j * (d + 1);
-  __shared__ long long red[256];
   __shared__ long long scnt[kSlots];  // points per slot row (biased sums)
-  __shared__ double rd[256], rn[256], re[256];
+  __shared__ long long sN;
+  __shared__ double wred[3][4];
   __shared__ int last;
-  long long v = 0;
-  if (tid < kSlots) {
-    v = col[(int64_t)tid * C + d];
-    col[(int64_t)tid * C + d] = 0;
-    scnt[tid] = v;
+  if (wv == 0) {
+    long long v = 0;
+    if (lane < kSlots) {
+      v = col[(int64_t)lane * C + d];
+      col[(int64_t)lane * C + d] = 0;
+      scnt[lane] = v;
+    }
+    v = wave_sum(v);
+    if (lane == 0) sN = v;
   }
-  red[tid] = v;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
-    __syncthreads();
-  }
-  const long long Nj = red[0];
-  __syncthreads();
+  const long long Nj = sN;
   const int F = st->F;
   double sh = 0.0, nn = 0.0, ee = 0.0;
   const int r = tid & 31, c = tid >> 5;  // 32 slots x 8 dims per round
@@ -2922,14 +2914,10 @@ __device__ void finalize_center(
       if (biased)
         sv = (long long)((unsigned long long)sv - (unsigned long long)scnt[r] * kSumBias);
     }
-    red[tid] = sv;
-    __syncthreads();
-    for (int o = 16; o > 0; o >>= 1) {
-      if (r < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
+    // the 32 slot rows of dim t are the lanes of one half wave
+    for (int o = 16; o > 0; o >>= 1) sv += __shfl_xor(sv, o);
     if (r == 0 && t < d) {
-      const double sum = ldexp((double)red[tid], -F);
+      const double sum = ldexp((double)sv, -F);
       if (update) {
         const double cold = c64[(int64_t)j * d + t];
         const double cnew = Nj > 0 ? sum / (double)Nj : cold;
@@ -2947,30 +2935,29 @@ __device__ void finalize_center(
       }
       if (S_out) S_out[(int64_t)j * d + t] = sum;
     }
-    __syncthreads();
   }
-  rd[tid] = sh;
-  rn[tid] = nn;
-  re[tid] = ee;
+  sh = wave_sum(sh);
+  nn = wave_sum(nn);
+  ee = wave_sum(ee);
+  if (lane == 0) {
+    wred[0][wv] = sh;
+    wred[1][wv] = nn;
+    wred[2][wv] = ee;
+  }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) {
-      rd[tid] += rd[tid + o];
-      rn[tid] += rn[tid + o];
-      re[tid] += re[tid + o];
-    }
-    __syncthreads();
-  }
   const bool new_copy = update && cb16;  // the BF16 copy of this center was rewritten
   if (tid == 0) {
+    const double rd0 = (wred[0][0] + wred[0][1]) + (wred[0][2] + wred[0][3]);
+    const double rn0 = (wred[1][0] + wred[1][1]) + (wred[1][2] + wred[1][3]);
+    const double re0 = (wred[2][0] + wred[2][1]) + (wred[2][2] + wred[2][3]);
     if (update) {
-      shiftj[j] = sqrt(rd[0]);
-      cn[j] = (float)rn[0];
-      cnorm[j] = sqrt(rn[0]);
+      shiftj[j] = sqrt(rd0);
+      cn[j] = (float)rn0;
+      cnorm[j] = sqrt(rn0);
       emptyj[j] = Nj == 0 ? 1 : 0;
-      if (cnB) cnB[j] = (float)(rn[0] + (double)st->B);
+      if (cnB) cnB[j] = (float)(rn0 + (double)st->B);
     }
-    if (new_copy) dcn_max(st, re[0]);
+    if (new_copy) dcn_max(st, re0);
     if (N_out) N_out[j] = (int64_t)Nj;
     __threadfence();
     last = atomicAdd(&st->ticket, 1u) == (unsigned)(k - 1) ? 1 : 0;
