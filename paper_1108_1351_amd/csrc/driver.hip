@@ -147,6 +147,31 @@ bool prof_on() {
   return g_prof.on;
 }
 
+// Per thread: two pass-state copies in pinned host memory and an event behind
+// each, for reading a chunk's state while the next chunk runs (kept for the
+// life of the thread, recreated if the thread moves to another device).
+struct StageSync {
+  PassState* h = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int dev = -1;
+};
+
+StageSync* stage_sync() {
+  thread_local StageSync ss;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  if (ss.dev != dev) {
+    if (!ss.h && hipHostMalloc(reinterpret_cast<void**>(&ss.h), 2 * sizeof(PassState)) != hipSuccess) {
+      ss.h = nullptr;
+      return nullptr;
+    }
+    for (hipEvent_t& e : ss.ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    ss.dev = dev;
+  }
+  return &ss;
+}
+
 struct StageResult {
   int32_t iters = 0, converged = 0, empty = 0;
   double J = 0.0, shift = 0.0;
@@ -161,6 +186,15 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
   int32_t launched = 0, chunk = 2;
   const int64_t rows = b.n;
   const bool prof = prof_on();
+  StageSync* ss = stage_sync();
+  int slot = 0, in_flight = 0;
+  auto drain = [&]() {  // the copies still in flight land before the buffers are reused
+    for (; in_flight > 0; --in_flight) {
+      const int old = (slot - in_flight) & 1;
+      (void)hipEventSynchronize(ss->ev[old]);
+    }
+  };
+  if (!ss) return fail(KM_EDEVICE, "pinned pass-state buffer or events unavailable");
   std::vector<hipEvent_t> ev;
   if (prof)
     for (int32_t i = 0; i < 3 * max_iter; ++i) ev.push_back(take_event());
@@ -170,23 +204,45 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
   if (copy16(plan)) HIP_TRY(prep_bf16(b.c64, b.k, b.d, plan.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * b.k * (b.d + 1), s));
   HIP_TRY(zero_i64(b.jslots, (int64_t)kSlots * 2, s));
-  while (launched < max_iter) {
-    const int32_t q = std::min(chunk, max_iter - launched);
-    for (int32_t i = 0; i < q; ++i) {
-      const int32_t t = launched + i;
-      if (prof && ev[3 * t]) HIP_TRY(hipEventRecord(ev[3 * t], s));
-      HIP_TRY(pass_assign(b, plan, true, s));
-      if (prof && ev[3 * t + 1]) HIP_TRY(hipEventRecord(ev[3 * t + 1], s));
-      HIP_TRY(pass_rest(b, plan, true, s));
-      if (prof && ev[3 * t + 2]) HIP_TRY(hipEventRecord(ev[3 * t + 2], s));
+  // Passes go out in chunks (2, 4, 8, then 16), each followed by a copy of the
+  // pass state.  One more chunk is queued before the host waits for a chunk's
+  // state, so the device does not idle while the host reads it; passes queued
+  // after the stop are gated and return at once.
+  while (true) {
+    if (launched < max_iter && in_flight < 2) {
+      const int32_t q = std::min(chunk, max_iter - launched);
+      for (int32_t i = 0; i < q; ++i) {
+        const int32_t t = launched + i;
+        if (prof && ev[3 * t]) HIP_TRY(hipEventRecord(ev[3 * t], s));
+        HIP_TRY(pass_assign(b, plan, true, s));
+        if (prof && ev[3 * t + 1]) HIP_TRY(hipEventRecord(ev[3 * t + 1], s));
+        HIP_TRY(pass_rest(b, plan, true, s));
+        if (prof && ev[3 * t + 2]) HIP_TRY(hipEventRecord(ev[3 * t + 2], s));
+      }
+      launched += q;
+      chunk = std::min(chunk * 2, 16);
+      HIP_TRY(hipMemcpyAsync(&ss->h[slot], b.st, sizeof(PassState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(ss->ev[slot], s));
+      slot ^= 1;
+      ++in_flight;
+      continue;
     }
-    launched += q;
-    chunk = std::min(chunk * 2, 16);
-    HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof hs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (hs.nonfinite) return fail(KM_EINVAL, "X contains NaN or Inf");
+    if (in_flight == 0) break;  // every pass ran and its state was read
+    const int old = (slot - in_flight) & 1;
+    const hipError_t e = hipEventSynchronize(ss->ev[old]);
+    --in_flight;
+    if (e != hipSuccess) {
+      rc = fail(KM_EDEVICE, "hipEventSynchronize failed: %s", hipGetErrorString(e));
+      goto done;
+    }
+    hs = ss->h[old];
+    if (hs.nonfinite) {
+      rc = fail(KM_EINVAL, "X contains NaN or Inf");
+      goto done;
+    }
     if (hs.done) break;
   }
+  drain();
   out->iters = hs.iter;
   out->converged = hs.converged;
   out->empty = hs.empty;
@@ -215,6 +271,7 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
     }
   }
 done:
+  drain();
   if (!ev.empty()) give_events(ev);
   return rc;
 }

@@ -1122,15 +1122,21 @@ __global__ __launch_bounds__(256) void k_run_sums(
       atomicAdd(reinterpret_cast<unsigned long long*>(&row[d]), (unsigned long long)cnt);
     cnt = 0;
   };
-  constexpr int R = 4;  // rows in flight per group
+  constexpr int R = 8;  // rows in flight per group
+  // the label order's row indices of the next R positions, loaded one batch
+  // ahead so that the row loads do not wait for them
+  uint32_t pidx[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) pidx[r] = p0 + r < p1 ? perm[p0 + r] : 0u;
   for (int64_t p = p0; p < p1; p += R) {
     float x[R][E];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const bool in = p + r < p1;
-      const int64_t i = in ? (int64_t)perm[p + r] : 0;
-      load_vec<T, E>(X + i * d + col, in && act, x[r]);
+      load_vec<T, E>(X + (int64_t)pidx[r] * d + col, in && act, x[r]);
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) pidx[r] = p + R + r < p1 ? perm[p + R + r] : 0u;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t pr = p + r;
