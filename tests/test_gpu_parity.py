@@ -116,6 +116,29 @@ def test_small_d_fused_paths(d, k, precision):
     assert abs(J2 - ref.J) <= 1e-12 * ref.J
 
 
+@pytest.mark.parametrize("d,k,dtype", [(8, 70, "f32"), (12, 90, "f32"), (16, 96, "bf16"),
+                                         (4, 33, "bf16"), (7, 128, "bf16"), (2, 3, "f32")])
+def test_split_screen_paths(d, k, dtype):
+    """The split screen (auto precision, d <= 16, k <= 128) over the shapes its
+    kernel is specialised for: 4, 8 or 16 padded dims, one to four 32-center
+    tiles, whole or padded rows, FP32 and BF16 data, a ragged last 64-point
+    block.  Labels, counts, exact sums (through the new centers) and J as the
+    oracle's."""
+    n = 30_001
+    print(f"[split paths] n={n} d={d} k={k} {dtype}", flush=True)
+    Xh = _mixture(n, d, min(k, 40), seed=d * 7 + k, dtype=dtype)
+    C = _centers_from(Xh, k, seed=k + 11, jitter=0.5)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    lab = out["labels"].cpu().numpy()
+    ex = exempt_mask(Xh, C)
+    assert np.array_equal(lab[~ex], ref.labels[~ex])
+    assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
+    if np.array_equal(lab, ref.labels):
+        assert np.array_equal(out["N"].cpu().numpy(), ref.N)
+        assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9, name="C_new")
+
+
 def test_step_bf16_input():
     Xh = _mixture(20_011, 64, 40, seed=3, dtype="bf16")
     C = _centers_from(Xh, 40, seed=4)
