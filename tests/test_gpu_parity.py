@@ -139,6 +139,29 @@ def test_split_screen_paths(d, k, dtype):
         assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9, name="C_new")
 
 
+@pytest.mark.parametrize("n", [1, 5, 63, 64, 65, 130])
+@pytest.mark.parametrize("k,d", [(1, 4), (2, 1), (3, 16), (5, 9)])
+def test_split_screen_tiny_inputs(n, k, d):
+    """Degenerate and ragged sizes on the split screen (auto precision): fewer
+    points than one 64-point block, one center (always certain), two centers
+    (no third key), d = 1 and 9 padded to 4 and 16 dims."""
+    if k > n:
+        pytest.skip("k > n is rejected")
+    rng = np.random.default_rng(n * 13 + k * 7 + d)
+    Xh = rng.normal(0, 3.0, size=(n, d)).astype(np.float32)
+    C = Xh[rng.choice(n, size=k, replace=False)].astype(np.float64) + 0.25
+    print(f"[split tiny] n={n} k={k} d={d}", flush=True)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    lab = out["labels"].cpu().numpy()
+    ex = exempt_mask(Xh, C)
+    assert np.array_equal(lab[~ex], ref.labels[~ex])
+    assert abs(out["J"] - ref.J) <= 1e-12 * max(ref.J, 1e-300)
+    if np.array_equal(lab, ref.labels):
+        assert np.array_equal(out["N"].cpu().numpy(), ref.N)
+        assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9, name="C_new")
+
+
 def test_step_bf16_input():
     Xh = _mixture(20_011, 64, 40, seed=3, dtype="bf16")
     C = _centers_from(Xh, 40, seed=4)
