@@ -2018,8 +2018,8 @@ inline bool full_row_ok(int kd, int d, const void* X) {
 // FP64 check of the uncertain points of a wave whose lanes hold whole rows
 // (KD values, zero past d): for each such lane in turn the wave scores all
 // centers (lane j takes centers j, j + 64, ...; FP64 centers in LDS with row
-// stride KD), then reduces to the smallest distance, lowest index on ties.
-template <int KD>
+// stride CSS), then reduces to the smallest distance, lowest index on ties.
+template <int KD, int CSS>
 __device__ __forceinline__ int64_t row_fp64_check(bool unc, const float (&x)[KD], int k,
                                                   const double* __restrict__ cs, int& label) {
   const int lane = threadIdx.x & 63;
@@ -2035,7 +2035,7 @@ __device__ __forceinline__ int64_t row_fp64_check(bool unc, const float (&x)[KD]
     double bD = INFINITY;
     int bj = INT_MAX;
     for (int j = lane; j < k; j += 64) {
-      const double* cj = cs + (int64_t)j * KD;
+      const double* cj = cs + (int64_t)j * CSS;
       double D = 0.0;
 #pragma unroll
       for (int t = 0; t < KD; ++t) {
@@ -2089,19 +2089,23 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
   constexpr int BG = BL + 1;                             // ... with the lane half
   constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
   extern __shared__ __align__(16) unsigned char smem[];
-  double* cs = reinterpret_cast<double*>(smem);  // [k][KD] FP64 centers, zero past d
-  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * KD);  // [k][d+1]
+  // [k][CSS] FP64 centers, zero past d: a row stride of KD + 2 doubles (an odd
+  // number of 16-byte units) spreads the rows that the lanes of a wave read for
+  // their own centers over the LDS banks
+  constexpr int CSS = KD + 2;
+  double* cs = reinterpret_cast<double*>(smem);
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * CSS);  // [k][d+1]
   // then, 16-byte aligned: the A operands [NT][NM][64 lanes] and the C input
   // [32 NT] (both read from LDS where the MFMAs need them, which keeps the
   // registers for two tiles of points)
-  const size_t tail = ((size_t)k * KD * 8 + (size_t)k * (d + 1) * 8 + 15) & ~(size_t)15;
+  const size_t tail = ((size_t)k * CSS * 8 + (size_t)k * (d + 1) * 8 + 15) & ~(size_t)15;
   v8bf* aop = reinterpret_cast<v8bf*>(smem + tail);
   float* cbias = reinterpret_cast<float*>(smem + tail + (size_t)NT * NM * 64 * 16);
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int e = threadIdx.x; e < k * KD; e += 256) {
     const int j = e / KD, t = e - j * KD;
-    cs[e] = t < d ? c64[(int64_t)j * d + t] : 0.0;
+    cs[j * CSS + t] = t < d ? c64[(int64_t)j * d + t] : 0.0;
   }
   if (update)
     for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
@@ -2117,7 +2121,7 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
     for (int u = 0; u < NE; ++u) e16[u] = 0;
 #pragma unroll
     for (int q = 0; q < H; ++q) {
-      const double cp = j < k ? -2.0 * cs[j * KD + hh * H + q] : 0.0;
+      const double cp = j < k ? -2.0 * cs[j * CSS + hh * H + q] : 0.0;
       const uint16_t hi = f32_to_bf16((float)cp);
       e16[q] = hi;
       e16[H + q] = f32_to_bf16((float)(cp - (double)__uint_as_float((uint32_t)hi << 16)));
@@ -2290,7 +2294,7 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
 #pragma unroll
     for (int q = 0; q < KD; ++q) x64[q] = (double)x[q];
     auto dist64 = [&](int j) {  // FP64 direct form over the whole row (zero past d)
-      const double* cj = cs + j * KD;
+      const double* cj = cs + j * CSS;
       double p = 0.0;
 #pragma unroll
       for (int q = 0; q < KD; ++q) {
@@ -2310,7 +2314,7 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
       pcnt += __popcll(__ballot(pair));
     }
     if (__ballot(full)) {
-      ucnt += row_fp64_check<KD>(full, x, k, cs, bi);
+      ucnt += row_fp64_check<KD, CSS>(full, x, k, cs, bi);
       if (full) p1 = dist64(bi);
     }
     if (valid) {
@@ -3364,9 +3368,11 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
     p.nt = (k + 31) / 32;
     p.lds_assign = kk * (size_t)std::max(p.kd, 2) * 8 + kk * (dd + 1) * 8;
     if (p.fsplit) {
-      // the paired-tile kernel also keeps its A operands and C input in LDS
+      // the paired-tile kernel: center rows of kd + 2 doubles, then its A
+      // operands and C input
       const size_t nm = (size_t)((dtype == 0 ? 3 : 2) * (p.kd / 2) + 7) / 8;
-      p.lds_assign = (p.lds_assign + 15) / 16 * 16 + (size_t)p.nt * nm * 64 * 16 + (size_t)p.nt * 32 * 4;
+      p.lds_assign = (kk * (size_t)(p.kd + 2) * 8 + kk * (dd + 1) * 8 + 15) / 16 * 16 +
+                     (size_t)p.nt * nm * 64 * 16 + (size_t)p.nt * 32 * 4;
     }
     work = p.fsplit ? ((rows + 63) / 64 + 3) / 4 : ((rows + 31) / 32 + 3) / 4;
   } else if (d <= 32 && k <= 128 && lds_mfma <= budget) {
