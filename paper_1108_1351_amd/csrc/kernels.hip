@@ -2073,7 +2073,7 @@ __device__ __forceinline__ int64_t row_fp64_check(bool unc, const float (&x)[KD]
 // distances decide between the two; otherwise the FP64 check over all centers
 // decides.  FULL: d == KD.
 template <typename T, int KD, int NT, bool FULL>
-__global__ __launch_bounds__(256, 3) void k_fused_pair(
+__global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
     const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cnB,
     const double* __restrict__ c64, const PassState* __restrict__ st,
     const int32_t* __restrict__ gate, int update, long long* __restrict__ slots,
@@ -2153,16 +2153,24 @@ __global__ __launch_bounds__(256, 3) void k_fused_pair(
   const int64_t npair = (n + 63) >> 6;
   const int64_t pstride = (int64_t)gridDim.x * 4;
   int64_t pp = (int64_t)blockIdx.x * 4 + wave;
-  float xnext[KD];
+  // rows of the next 64 points load while this wave works on the current ones,
+  // except for whole 16-dim rows, where those registers buy a fourth wave per
+  // SIMD instead (measured faster)
+  constexpr bool PREF = !(KD == 16 && FULL);
+  float xnext[PREF ? KD : 1];
   // rows past n read the last row (their results are not used)
-  load_row_full<T, KD, FULL>(X, min((pp << 6) + lane, n - 1), d, xnext);
+  if constexpr (PREF) load_row_full<T, KD, FULL>(X, min((pp << 6) + lane, n - 1), d, xnext);
   for (; pp < npair; pp += pstride) {
     const int64_t i = (pp << 6) + lane;
     const bool valid = i < n;
     float x[KD];
+    if constexpr (PREF) {
 #pragma unroll
-    for (int q = 0; q < KD; ++q) x[q] = xnext[q];
-    load_row_full<T, KD, FULL>(X, min(((pp + pstride) << 6) + lane, n - 1), d, xnext);
+      for (int q = 0; q < KD; ++q) x[q] = xnext[q];
+      load_row_full<T, KD, FULL>(X, min(((pp + pstride) << 6) + lane, n - 1), d, xnext);
+    } else {
+      load_row_full<T, KD, FULL>(X, min(i, n - 1), d, x);
+    }
     // the row as BF16: x^ (RNE, two values per instruction) and, for FP32 data,
     // xlo = BF16(x - x^) (the difference is exact); packed word w holds dims
     // 2w, 2w + 1, so words [0, HW) are the first half row
