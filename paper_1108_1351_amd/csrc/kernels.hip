@@ -1387,12 +1387,15 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
   constexpr int BG = BL + 1;                            // bits of a center index (32*NT centers)
   constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
   extern __shared__ __align__(16) unsigned char smem[];
-  double* cs = reinterpret_cast<double*>(smem);  // [k][KD] FP64 centers, zero past d
-  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * KD);  // [k][d+1]
+  // [k][CSS] FP64 centers, zero past d (rows padded to an odd number of 16-byte
+  // units, so that the lanes' reads of their own centers spread over the banks)
+  constexpr int CSS = KD + 2;
+  double* cs = reinterpret_cast<double*>(smem);
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * CSS);  // [k][d+1]
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < k * KD; e += 256) {
     const int j = e / KD, t = e - j * KD;
-    cs[e] = t < d ? c64[(int64_t)j * d + t] : 0.0;
+    cs[j * CSS + t] = t < d ? c64[(int64_t)j * d + t] : 0.0;
   }
   if (update)
     for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
@@ -1484,7 +1487,7 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
     const bool full = valid && !certain && !pair;
     if (bi >= k) bi = 0;
     auto dist64 = [&](int j) {  // FP64 direct form over this lane's dims (zero past d)
-      const double* cj = cs + j * KD + h * H;
+      const double* cj = cs + j * CSS + h * H;
       double p = 0.0;
 #pragma unroll
       for (int q = 0; q < H; ++q) {
@@ -1505,7 +1508,7 @@ __global__ __launch_bounds__(256) void k_fused_mfma(
       pcnt += __popcll(__ballot(pair && h == 0));
     }
     if (__ballot(full)) {
-      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi, KD);
+      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi, CSS);
       const int bfull = __shfl(bi, pc);
       if (full) {
         bi = bfull < k ? bfull : 0;
@@ -1802,12 +1805,15 @@ __global__ __launch_bounds__(256, NT > 3 ? 2 : 3) void k_fused_screen(
   constexpr int BG = BL + 1;                            // bits of a center index (32*NT centers)
   constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
   extern __shared__ __align__(16) unsigned char smem[];
-  double* cs = reinterpret_cast<double*>(smem);  // [k][KD] FP64 centers, zero past d
-  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * KD);  // [k][d+1]
+  // [k][CSS] FP64 centers, zero past d (rows padded to an odd number of 16-byte
+  // units, so that the lanes' reads of their own centers spread over the banks)
+  constexpr int CSS = KD + 2;
+  double* cs = reinterpret_cast<double*>(smem);
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(cs + (size_t)k * CSS);  // [k][d+1]
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31, wave = threadIdx.x >> 6;
   for (int e = threadIdx.x; e < k * KD; e += 256) {
     const int j = e / KD, t = e - j * KD;
-    cs[e] = t < d ? c64[(int64_t)j * d + t] : 0.0;
+    cs[j * CSS + t] = t < d ? c64[(int64_t)j * d + t] : 0.0;
   }
   if (update)
     for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
@@ -1823,7 +1829,7 @@ __global__ __launch_bounds__(256, NT > 3 ? 2 : 3) void k_fused_screen(
     u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int q = 0; q < H; ++q)
-      v[q] = f32_to_bf16((float)(j < k ? -2.0 * cs[j * KD + h * H + q] : 0.0));
+      v[q] = f32_to_bf16((float)(j < k ? -2.0 * cs[j * CSS + h * H + q] : 0.0));
     a[t] = __builtin_bit_cast(v8bf, v);
 #pragma unroll
     for (int r = 0; r < 16; ++r) bias[t][r] = cnB[32 * t + 8 * (r >> 2) + 4 * h + (r & 3)];
@@ -1922,7 +1928,7 @@ __global__ __launch_bounds__(256, NT > 3 ? 2 : 3) void k_fused_screen(
     const bool full = valid && !certain && !pair;
     if (bi >= k) bi = 0;
     auto dist64 = [&](int j) {  // FP64 direct form over this lane's dims (zero past d)
-      const double* cj = cs + j * KD + h * H;
+      const double* cj = cs + j * CSS + h * H;
       double p = 0.0;
 #pragma unroll
       for (int q = 0; q < H; ++q) {
@@ -1943,7 +1949,7 @@ __global__ __launch_bounds__(256, NT > 3 ? 2 : 3) void k_fused_screen(
       pcnt += __popcll(__ballot(pair && h == 0));
     }
     if (__ballot(full)) {
-      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi, KD);
+      ucnt += mfma_fp64_check<H>(full && h == 0, x, d, k, cs, bi, CSS);
       const int bfull = __shfl(bi, pc);
       if (full) {
         bi = bfull < k ? bfull : 0;
@@ -3345,7 +3351,7 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   // codes follow km_precision: 0 auto, 1 FP32, 2 BF16 screen)
   const bool screen = precision == 2 || (precision == 0 && dtype == 1 && d >= 32);
   const bool small = d <= 16 && k <= 128 &&
-                     kk * (size_t)std::max(p.dmax, 2) * 8 + kk * (dd + 1) * 8 <= budget;
+                     kk * (size_t)(std::max(p.dmax, 2) + 2) * 8 + kk * (dd + 1) * 8 <= budget;
   p.bf16 = d <= 256 && screen && !small;
   if (p.bf16) {
     p.ks = d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 4 : d <= 128 ? 8 : 16;
@@ -3353,7 +3359,8 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   }
   // fused MFMA passes (d <= 32, k <= 128): FP64 centers padded to the kernel's
   // dims, and the sums with counts
-  const size_t lds_mfma = kk * (size_t)std::max(p.dmax, 2) * 8 + kk * (dd + 1) * 8;
+  // (center rows of the fused MFMA and screen passes: kd + 2 doubles)
+  const size_t lds_mfma = kk * (size_t)(std::max(p.dmax, 2) + 2) * 8 + kk * (dd + 1) * 8;
   const size_t lds_fused = ((kk * (size_t)p.dmax + kk) * 4 + 15) / 16 * 16 + kk * (dd + 1) * 8;
   int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
   if (p.bf16) {
@@ -3374,7 +3381,7 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
     p.kd = p.fsplit ? std::max(p.dmax, 4) : p.dmax;
     p.d = d;
     p.nt = (k + 31) / 32;
-    p.lds_assign = kk * (size_t)std::max(p.kd, 2) * 8 + kk * (dd + 1) * 8;
+    p.lds_assign = kk * (size_t)(std::max(p.kd, 2) + 2) * 8 + kk * (dd + 1) * 8;
     if (p.fsplit) {
       // the paired-tile kernel: center rows of kd + 2 doubles, then its A
       // operands and C input
