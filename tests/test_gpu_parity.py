@@ -162,6 +162,26 @@ def test_split_screen_tiny_inputs(n, k, d):
         assert_centers(out["C_new"].cpu().numpy(), ref.C_new, Xh, tol=1e-9, name="C_new")
 
 
+@pytest.mark.parametrize("d,k", [(16, 64), (4, 32), (8, 20)])
+def test_split_screen_misaligned_rows(d, k):
+    """X starting 4 bytes past a 16-byte boundary: the split screen cannot load
+    whole rows as aligned vectors and takes its element-load path."""
+    n = 10_007
+    Xh = _mixture(n, d, min(k, 20), seed=d + k)
+    flat = torch.empty(n * d + 1, dtype=torch.float32, device="cuda")
+    flat[1:] = torch.from_numpy(Xh.reshape(-1)).cuda()
+    X = flat[1:].view(n, d)
+    assert X.data_ptr() % 16 == 4
+    C = _centers_from(Xh, k, seed=k, jitter=0.5)
+    print(f"[split misaligned] n={n} d={d} k={k}", flush=True)
+    out = km.km_step(X, torch.from_numpy(C).cuda())
+    ref = oracle.step(Xh, C)
+    lab = out["labels"].cpu().numpy()
+    ex = exempt_mask(Xh, C)
+    assert np.array_equal(lab[~ex], ref.labels[~ex])
+    assert abs(out["J"] - ref.J) <= 1e-12 * ref.J
+
+
 def test_step_bf16_input():
     Xh = _mixture(20_011, 64, 40, seed=3, dtype="bf16")
     C = _centers_from(Xh, 40, seed=4)
