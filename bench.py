@@ -10,12 +10,14 @@ per second of the whole job: k*(m*Q_f + n*Q_s) + k*n evaluations per fit
 fit's wall time.
 
 The roofline object covers the dominant kernel, the slow stage's assignment
-kernel (for BF16 data, its BF16 MFMA screen): its duration is measured live with HIP events on the stream it
-runs on (the library's pass profiler).  Its algorithmic work per launch is
-2*n*k*d flops and n*d*s bytes (s = bytes per element of X); the bound is
-whichever of HBM bandwidth and the arithmetic peak (dense BF16 MFMA for the
-screen, FP32 for the FP32 kernels) allows less.  The CPU baseline is the FP64 oracle timed on a bounded sample of the
-same workload on the host's cores.
+kernel (for BF16 data with d >= 32, its BF16 MFMA screen; for d <= 16 and
+k <= 128, the fused pass on the split BF16 screen): its duration is measured
+live with HIP events on the stream it runs on (the library's pass profiler).
+Its algorithmic work per launch is 2*n*k*d flops and n*d*s bytes (s = bytes
+per element of X); the bound is whichever of HBM bandwidth and the arithmetic
+peak (dense BF16 MFMA for the BF16 screen, FP32 otherwise) allows less.  The
+CPU baseline is the FP64 oracle timed on a bounded sample of the same workload
+on the host's cores.
 """
 from __future__ import annotations
 
