@@ -2091,9 +2091,8 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
   constexpr int NS = sizeof(T) == 4 ? 3 : 2;             // products per dim
   constexpr int NM = (NS * H + 7) / 8;                   // MFMAs per center tile
   constexpr int NE = NM * 8;                             // K elements per lane half
-  constexpr int BL = NT == 1 ? 4 : (NT == 2 ? 5 : 6);   // bits of a lane-local index
-  constexpr int BG = BL + 1;                             // ... with the lane half
-  constexpr int LM = (1 << BL) - 1, GM = (1 << BG) - 1;
+  constexpr int BG = NT == 1 ? 5 : (NT == 2 ? 6 : 7);   // bits of a center index (32 NT)
+  constexpr int GM = (1 << BG) - 1;
   extern __shared__ __align__(16) unsigned char smem[];
   // [k][CSS] FP64 centers, zero past d: a row stride of KD + 2 doubles (an odd
   // number of 16-byte units) spreads the rows that the lanes of a wave read for
@@ -2117,11 +2116,14 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
     for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
   for (int e = threadIdx.x; e < 32 * NT; e += 256) cbias[e] = cnB[e];
   __syncthreads();
-  // A operand of lane ln, center tile t: center row 32t + ln % 32, dims
-  // hH .. hH + H - 1 (h = ln / 32); K elements c'hi, c'lo and, for FP32 data,
-  // c'hi again, each over the half's H dims
+  // A operand of lane ln, center tile t, dims hH .. hH + H - 1 (h = ln / 32); K
+  // elements c'hi, c'lo and, for FP32 data, c'hi again, each over the half's H
+  // dims.  Row i = ln % 32 of the tile holds center 32t + 16 ((i / 4) % 2) +
+  // 4 (i / 8) + i % 4: output register r of lane half h (row 8 (r / 4) + 4h +
+  // r % 4) is then center 32t + 16h + r, so a key's low bits are its center.
   for (int e = threadIdx.x; e < NT * 64; e += 256) {
-    const int t = e >> 6, ln = e & 63, hh = ln >> 5, j = 32 * t + (ln & 31);
+    const int t = e >> 6, ln = e & 63, hh = ln >> 5, i = ln & 31;
+    const int j = 32 * t + 16 * ((i >> 2) & 1) + 4 * (i >> 3) + (i & 3);
     uint16_t e16[NE];
 #pragma unroll
     for (int u = 0; u < NE; ++u) e16[u] = 0;
@@ -2235,7 +2237,7 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         // the value part drops BG bits (the index bits and the lane half)
-        const int kv = (__float_as_int(acc[r]) & ~GM) | (16 * t + r);
+        const int kv = (__float_as_int(acc[r]) & ~GM) | (32 * t + r);
         m3 = med3_i32(m2, kv, m3);
         m2 = med3_i32(m1, kv, m2);
         m1 = min(m1, kv);
@@ -2243,11 +2245,11 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
     };
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      // the C input of this lane's rows 8(r/4) + 4h + r%4 of tile t
+      // the C input of this lane's centers 32t + 16h + r
       v16f bias;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const float4 v = *reinterpret_cast<const float4*>(&cbias[32 * t + 8 * g + 4 * h]);
+        const float4 v = *reinterpret_cast<const float4*>(&cbias[32 * t + 16 * h + 4 * g]);
         bias[4 * g] = v.x; bias[4 * g + 1] = v.y; bias[4 * g + 2] = v.z; bias[4 * g + 3] = v.w;
       }
       v8bf at = aop[(t * NM) * 64 + lane];
@@ -2262,9 +2264,9 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
       rank(accA, t, a1, a2, a3);
       rank(accB, t, b1, b2, b3);
     }
-    // the lane half into the index bits, then swap: lane l gets the other
-    // half's keys of its own point and merges
-    const int hb = h << BL;
+    // the lane half into the index bits (which then hold the center), then
+    // swap: lane l gets the other half's keys of its own point and merges
+    const int hb = h << 4;
     int g1, g2, g3;
     {
       const auto s1 = __builtin_amdgcn_permlane32_swap(a1 | hb, b1 | hb, false, false);
@@ -2281,12 +2283,7 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
         g1 = min(g1, ov[u]);
       }
     }
-    // index bits -> center: local slot l of lane half hh is row
-    // 32 (l / 16) + 8 ((l % 16) / 4) + 4 hh + l % 4
-    auto center = [&](int key) {
-      const int l = key & LM, hh = (key >> BL) & 1;
-      return 32 * (l >> 4) + 8 * ((l & 15) >> 2) + 4 * hh + (l & 3);
-    };
+    auto center = [&](int key) { return key & GM; };
     int bi = center(g1);
     const int bj2 = center(g2);
     const float v1 = __int_as_float(g1 & ~GM), v2 = __int_as_float(g2 & ~GM),
