@@ -2070,8 +2070,8 @@ __device__ __forceinline__ int64_t row_fp64_check(bool unc, const float (&x)[KD]
 // A wave takes 64 consecutive points; lane l loads the whole row of point l and
 // rounds it.  One permlane32 swap per packed word gives each lane half its
 // operand halves of both 32-point tiles (tile A: points 0..31, tile B: 32..63).
-// Each lane ranks its 16 NT scores of both tiles (best three as integer keys,
-// score bits with the slot and the lane half in the low bits); one swap per key
+// Each lane ranks its 16 NT scores of both tiles (best three as integer keys:
+// score bits with the center index in the low bits); one swap per key
 // then hands lane l the other half's keys of its own point (lane half 0
 // finishes tile A, half 1 tile B), so the merge, the error band, the FP64
 // decisions, J and the cluster sums run once per point, on whole rows.  The
