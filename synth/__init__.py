@@ -1,7 +1,7 @@
 """Seeded synthetic Gaussian-mixture inputs (a test and benchmark fixture).
 
 This module produces input data only: it holds no clustering arithmetic and is
-shared by the CPU checker and by the GPU library's tests and benchmark.  The
+shared by the CPU oracle and by the GPU library's tests and benchmark.  The
 generator itself is C (``synth.c``, counter-based SplitMix64 + Box-Muller),
 so any row range of any workload can be regenerated bit-identically.
 

@@ -1,7 +1,7 @@
 /*
  * Seeded synthetic Gaussian-mixture generator.
  *
- * Input fixture for the k-means library and for its checker: it produces the
+ * Input fixture for the k-means library and for its FP64 oracle: it produces the
  * data matrix X only and holds none of the clustering arithmetic.  Every value
  * is a pure function of (seed, stream, counter), so any row range can be
  * generated on its own, by any number of threads, with identical bits.
