@@ -145,6 +145,87 @@ def serve_stream(count: int, rate: float, budget: int) -> dict:
             "peak_active": st["peak_active"], "peak_bytes": st["peak_bytes"]}
 
 
+SPEEDUP_TOLS = [10.0 ** -e for e in range(1, 11)]
+SPEEDUP_FRACS = [0.10, 0.15, 0.20, 0.30, 0.40]
+SPEEDUP_SIZES = [1_000_000, 2_000_000, 5_000_000, 10_000_000]
+
+
+def speedup_specs():
+    """The sweep's data: (grid name, mixture spec, k, data seed)."""
+    import synth
+    spec10 = synth.MixtureSpec(10, 10, "uniform", -10.0, 10.0, sigma_lo=0.5, sigma_hi=2.0)
+    spec12 = synth.MixtureSpec(12, 12, "uniform", -10.0, 10.0, sigma_lo=0.5, sigma_hi=2.0)
+    return {"table2": ("table2_10d", spec10, 10, 1010), "sec61": ("sec61_12d", spec12, 12, 1012)}
+
+
+SPEEDUP_FIT_SEED = 7
+
+
+def speedup_sweep(reps: int = 3, max_iter: int = 1000, table2_n: int = 100_000,
+                  fracs=None, tols=None, sizes=None, sec61_frac: float = 0.01,
+                  sec61_tol: float = 1e-4) -> list:
+    """The two-stage method against normal k-means (the slow stage alone, from the
+    same initial centers) on the same kernels (section 6 and its Table 2;
+    section 6.1).  Stand-ins for the paper's data (not available): a 10-D
+    mixture of 100,000 points (10 equally weighted components, means
+    U[-10,10]^10, sigma_c U[0.5,2], k = 10) swept over the subset fraction and
+    the stopping tolerance (the same tolerance in both stages and in normal
+    k-means); and 12-D mixtures of 1e6..1e7 points (12 components, the same
+    distribution in 12-D, k = 12, 1% subset, tolerance 1e-4).  Each cell runs
+    both fits `reps` times and keeps the median wall time; the evals ratio is
+    the machine-independent form of the speed-up (section 3's cost model)."""
+    import numpy as np
+    import torch
+
+    import paper_1108_1351_amd as km
+    import synth
+
+    def load(spec, n, seed):
+        Xh = synth.generate(spec, seed, n, "f32")
+        return torch.from_numpy(Xh).to("cuda")
+
+    def fit(X, k, f, tol, normal):
+        ts, info = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = km.kmeans_fit_ex(X, k, f, SPEEDUP_FIT_SEED, max_iter, tol,
+                                          skip_stage1=normal,
+                                          labels=True)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), info
+
+    def cell(name, X, k, f, tol):
+        t2, i2 = fit(X, k, f, tol, False)
+        t1, i1 = fit(X, k, f, tol, True)
+        row = {"grid": name, "n": int(X.shape[0]), "d": int(X.shape[1]), "k": k,
+               "subset_frac": f, "tol": tol, "max_iter": max_iter,
+               "two_stage": {"s": t2, "passes": i2["iters"], "evals": i2["dist_evals"],
+                             "J": i2["J"]},
+               "normal": {"s": t1, "passes": i1["iters"][1], "evals": i1["dist_evals"],
+                          "J": i1["J"]},
+               "speedup_time": t1 / t2, "speedup_evals": i1["dist_evals"] / i2["dist_evals"]}
+        print(f"[speedup] {name} n={row['n']} f={f:g} tol={tol:g}: time x{row['speedup_time']:.2f}"
+              f" evals x{row['speedup_evals']:.2f}", file=sys.stderr, flush=True)
+        return row
+
+    rows = []
+    specs = speedup_specs()
+    name, spec, k, seed = specs["table2"]
+    X = load(spec, table2_n, seed)
+    for f in fracs or SPEEDUP_FRACS:
+        for tol in tols or SPEEDUP_TOLS:
+            rows.append(cell(name, X, k, f, tol))
+    del X
+    name, spec, k, seed = specs["sec61"]
+    for n in sizes or SPEEDUP_SIZES:
+        X = load(spec, n, seed)
+        rows.append(cell(name, X, k, sec61_frac, sec61_tol))
+        del X
+    return rows
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,7 +241,16 @@ def main() -> int:
                     help="run the serving stream of REQUESTS requests instead of the fit bench")
     ap.add_argument("--serve-rate", type=float, default=100.0, help="arrivals per second")
     ap.add_argument("--serve-budget", type=int, default=0, help="server HBM budget (bytes)")
+    ap.add_argument("--speedup", action="store_true",
+                    help="run the two-stage vs normal k-means sweep instead of the fit bench")
     args = ap.parse_args()
+    if args.speedup:
+        if args.gpus != 1:
+            print("bench.py measures one GPU", file=sys.stderr)
+            return 2
+        for row in speedup_sweep():
+            print(json.dumps(row), flush=True)
+        return 0
     if args.serve:
         if args.gpus != 1:
             print("bench.py measures one GPU", file=sys.stderr)

@@ -282,6 +282,27 @@ def test_fit_normal_mode_and_resume():
     assert_centers(info["centers64"].cpu().numpy(), ref.centers, Xh)
 
 
+def test_speedup_sweep_cells_match_oracle():
+    """The two-stage vs normal k-means sweep: both fits of a cell run the
+    oracle's passes and evaluations, so the evals ratio is the oracle's."""
+    import bench
+    rows = bench.speedup_sweep(reps=1, max_iter=200, table2_n=20_000, fracs=[0.1],
+                               tols=[1e-2, 1e-4], sizes=[30_000], sec61_frac=0.05)
+    assert len(rows) == 3
+    specs = bench.speedup_specs()
+    for row in rows:
+        key = "table2" if row["grid"].startswith("table2") else "sec61"
+        _, spec, k, seed = specs[key]
+        print(f"[speedup] {row['grid']} n={row['n']} tol={row['tol']}", flush=True)
+        Xh = synth.generate(spec, seed, row["n"], "f32")
+        for mode, normal in (("two_stage", False), ("normal", True)):
+            ref = oracle.fit(Xh, k, row["subset_frac"], bench.SPEEDUP_FIT_SEED, row["max_iter"],
+                             row["tol"], skip_stage1=normal)
+            assert row[mode]["evals"] == ref.info["dist_evals"], (mode, row[mode], ref.info)
+            assert abs(row[mode]["J"] - ref.info["J"]) <= JTOL * ref.info["J"] + j_atol(Xh)
+        assert row["speedup_evals"] == row["normal"]["evals"] / row["two_stage"]["evals"]
+
+
 def test_fit_per_stage_tolerances():
     w = synth.WORKLOADS["gmm2d_n1e5_k8"].scaled(30_000)
     Xh = w.data()
