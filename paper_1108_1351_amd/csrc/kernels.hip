@@ -1671,11 +1671,19 @@ __device__ __forceinline__ int rerank_vec(const T* __restrict__ xr, int d,
                                           const float* __restrict__ cw,
                                           const double* __restrict__ c64, float cmax,
                                           int64_t& fp64_count) {
+  // BF16 data: the lane's dims 16 s + 8 h + e, read once for all candidates
+  uint4 xw[KS];
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int t0 = 16 * s + 8 * h;
+      xw[s] = t0 < d ? *reinterpret_cast<const uint4*>(xr + t0) : make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
   // the lane's values: dims 16 s + 8 h + e
   auto xval = [&](int s, float (&v)[8]) {
     if constexpr (sizeof(T) == 2) {
-      const int t0 = 16 * s + 8 * h;
-      const uint4 w = t0 < d ? *reinterpret_cast<const uint4*>(xr + t0) : make_uint4(0u, 0u, 0u, 0u);
+      const uint4 w = xw[s];
       const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
