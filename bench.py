@@ -3,21 +3,25 @@
 
 A step is one complete two-stage fit -- fast-stage sampling, the fast stage on
 the subset, the slow stage on all points, the final labelling pass -- of a
-Gaussian-mixture workload (default: 10,000,000 x 16-D FP32, k = 64), with X
-resident in HBM before the timed region.  ``value`` is distance evaluations
-per second of the whole job: k*(m*Q_f + n*Q_s) + k*n evaluations per fit
-(section 3 of the paper counts the method's cost in these units) over the
-fit's wall time.
+Gaussian-mixture workload (default: the largest single-GPU one,
+100,000,000 x 128-D BF16, k = 1024), with X resident in HBM before the timed
+region.  ``value`` is distance evaluations per second of the whole job:
+k*(m*Q_f + n*Q_s) + k*n evaluations per fit (section 3 of the paper counts the
+method's cost in these units) over the fit's wall time.
 
 The roofline object covers the dominant kernel, the slow stage's assignment
 kernel (for BF16 data with d >= 32, its BF16 MFMA screen; for d <= 16 and
 k <= 128, the fused pass on the split BF16 screen): its duration is measured
 live with HIP events on the stream it runs on (the library's pass profiler).
 Its algorithmic work per launch is 2*n*k*d flops and n*d*s bytes (s = bytes
-per element of X); the bound is whichever of HBM bandwidth and the arithmetic
-peak (dense BF16 MFMA for the BF16 screen, FP32 otherwise) allows less.  The
-CPU baseline is the FP64 oracle timed on a bounded sample of the same workload
-on the host's cores.
+per element of X).  It is priced against the unit its products run on:
+T_roof = max(bytes / HBM peak, flops / peak of that unit) -- dense BF16 MFMA
+for the BF16 screens (the split screen included), FP32 MFMA for the FP32 MFMA
+pass, FP32 vector otherwise -- and frac = T_roof / measured duration.  The
+VALU issue load of the kernel, from the committed counter summary, is a field
+of its own.  Measured peaks (a streaming read, a BF16 MFMA loop) are reported
+beside the datasheet ones.  The CPU baseline is the FP64 oracle timed on a
+bounded sample of the same workload on the host's cores.
 """
 from __future__ import annotations
 
@@ -31,13 +35,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = "gmm16d_n1e7_k64"
+WORKLOAD = "gmm128d_n1e8_k1024_bf16"
 PEAK_FP32_TFLOPS = 157.3        # MI355X published FP32 vector/matrix peak
 PEAK_BF16_TFLOPS = 2500.0       # MI355X published dense BF16 MFMA peak
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
+# VALU issue: one wave64 instruction per SIMD per 4 cycles, 1024 SIMDs at 2.4 GHz
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 # rows of the CPU-baseline sample per workload (about 10-30 s of oracle work)
 CPU_ROWS = {"gmm2d_n1e5_k8": 100_000, "gmm16d_n1e7_k64": 2_000_000,
-            "gmm128d_n1e8_k1024_bf16": 40_000, "gmm4d_n5e8_k32": 20_000_000}
+            "gmm128d_n1e8_k1024_bf16": 80_000, "gmm4d_n5e8_k32": 20_000_000}
 METRIC = "distance evals/s & % roofline per Lloyd iter; batched p50/p99 solve latency"
 
 
@@ -49,10 +55,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when it is absent or the kernel source has changed since."""
-    path = os.path.join(ROOT, "profiles", f"traffic_assign_{workload}.txt")
+def _profile_kv(name: str):
+    """key value lines of a committed counter summary, or None when it is absent
+    or the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -62,10 +68,57 @@ def read_traffic(workload: str):
             kv[parts[0]] = parts[1]
     if kv.get("kernel_src_sha256") != kernel_source_hash():
         return None
+    return kv
+
+
+def read_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy's readings), or None."""
+    kv = _profile_kv(f"traffic_assign_{workload}.txt")
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+def read_valu(workload: str):
+    """SQ_INSTS_VALU per launch of the dominant kernel, or None."""
+    kv = _profile_kv(f"valu_assign_{workload}.txt")
+    try:
+        return float(kv["valu_insts_per_launch"]) if kv else None
+    except (KeyError, ValueError):
+        return None
+
+
+def plan_unit(dtype: str, d: int, k: int, precision: str):
+    """The pass the library plans for the slow stage, and the unit its products
+    run on: (kernel description, unit name, unit peak TFLOP/s, dtype label)."""
+    screen = precision == "bf16_rerank" or (precision == "auto" and dtype == "bf16" and d >= 32)
+    small = d <= 16 and k <= 128
+    if small and precision in ("auto", "bf16_rerank"):
+        if precision == "auto":
+            return ("slow-stage fused pass on the split BF16 screen (c'hi x^ + c'lo x^ + c'hi xlo "
+                    "on BF16 MFMA, FP32 accumulate, certified top-3 keys, FP64 decisions, J and "
+                    "exact cluster sums)", "bf16 mfma", PEAK_BF16_TFLOPS, "bf16x3-split")
+        return ("slow-stage fused pass on the BF16 screen", "bf16 mfma", PEAK_BF16_TFLOPS, "bf16")
+    if screen and d <= 256:
+        return ("slow-stage BF16 MFMA screen (slot-pair top-2 keys, certified candidates, "
+                "FP64 re-rank)", "bf16 mfma", PEAK_BF16_TFLOPS, "bf16")
+    if d <= 32 and k <= 128:
+        return ("slow-stage fused pass on FP32 MFMA (assign + cluster sums)", "fp32 mfma",
+                PEAK_FP32_TFLOPS, "f32")
+    return ("slow-stage FP32 assignment kernel", "fp32 valu", PEAK_FP32_TFLOPS, "f32")
+
+
+def measured_peaks():
+    """A streaming read of 2 GiB and a BF16 MFMA loop, timed on this GPU."""
+    import torch
+
+    import paper_1108_1351_amd as km
+    buf = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+    hbm = km.km_probe_stream_read(buf, reps=10)
+    del buf
+    return {"hbm_read_GBs": hbm, "bf16_mfma_TFLOPs": km.km_probe_mfma_bf16(20000)}
 
 
 def cpu_baseline(w, rows: int):
@@ -232,6 +285,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16_rerank"],
+                    help="the library's precision choice (fp32: the plain FP32 path)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured-peak probes")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="rows of the CPU-baseline sample (default: per workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -305,7 +361,7 @@ def main() -> int:
 
     def step():
         return km.kmeans_fit_ex(X, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol,
-                                labels=True)
+                                labels=True, precision=args.precision)
 
     for i in range(args.warmup):
         step()
@@ -333,34 +389,36 @@ def main() -> int:
     rows = prof["rows"][1] / max(1, launches)
     flops = 2.0 * rows * w.k * w.d
     algo_bytes = rows * w.d * (4 if w.dtype == "f32" else 2)
-    # the pass the library plans at auto precision: the BF16 screen (BF16 data,
-    # d >= 32), the fused split BF16 screen (d <= 16, k <= 128) or the FP32 kernels
-    bf16_screen = w.dtype == "bf16" and w.d >= 32
-    split_screen = w.d <= 16 and w.k <= 128
-    peak_flops = PEAK_BF16_TFLOPS if bf16_screen else PEAK_FP32_TFLOPS
-    traffic = read_traffic(w.name)
-    if algo_bytes / (PEAK_HBM_GBS * 1e9) > flops / (peak_flops * 1e12):
+    kernel, unit, peak_flops, dtype_label = plan_unit(w.dtype, w.d, w.k, args.precision)
+    traffic = read_traffic(w.name) if args.precision == "auto" else None
+    # T_roof = max(bytes / HBM peak, flops / peak of the unit the products run on)
+    t_hbm = algo_bytes / (PEAK_HBM_GBS * 1e9)
+    t_unit = flops / (peak_flops * 1e12)
+    if t_hbm >= t_unit:
         achieved = algo_bytes / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     else:
         achieved = flops / avg_s / 1e12
-        roofline = {"bound": "mfma" if bf16_screen else "alu",
+        roofline = {"bound": "mfma" if "mfma" in unit else "alu",
                     "achieved": achieved, "peak": peak_flops, "unit": "TFLOP/s"}
-    if bf16_screen:
-        kernel = ("slow-stage BF16 MFMA screen (slot-pair top-2 keys, certified candidates, "
-                  "FP32/FP64 re-rank)")
-    elif split_screen:
-        kernel = ("slow-stage fused pass on the split BF16 screen (c'hi x^ + c'lo x^ + c'hi xlo "
-                  "on BF16 MFMA, FP32 accumulate, certified top-3 keys, FP64 decisions, J and "
-                  "exact cluster sums)")
-    else:
-        kernel = "slow-stage assignment kernel (fused assign + cluster sums)"
+    valu = read_valu(w.name) if args.precision == "auto" else None
     roofline.update({
         "frac": roofline["achieved"] / roofline["peak"], "traffic": traffic,
-        "kernel": kernel,
+        "kernel": kernel, "products_on": unit,
+        "T_roof_us": max(t_hbm, t_unit) * 1e6,
         "launches": launches, "avg_launch_us": avg_s * 1e6,
         "flops_per_launch": flops, "algo_bytes_per_launch": algo_bytes,
-        "achieved_TFLOPs": flops / avg_s / 1e12, "algo_hbm_GBs": algo_bytes / avg_s / 1e9})
+        "achieved_TFLOPs": flops / avg_s / 1e12, "algo_hbm_GBs": algo_bytes / avg_s / 1e9,
+        # VALU instructions per launch (counters) over what the SIMDs can issue
+        # in the measured duration: the issue load, not a roofline
+        "valu_issue_util": (valu / (avg_s * VALU_ISSUE_PER_S)) if valu else None})
+    if not args.no_peaks:
+        mp = measured_peaks()
+        roofline["measured_peaks"] = mp
+        roofline["frac_of_measured"] = (
+            roofline["achieved"] / (mp["hbm_read_GBs"] if roofline["bound"] == "hbm"
+                                    else mp["bf16_mfma_TFLOPs"])
+            if roofline["bound"] != "alu" else None)
     pass_s = prof["pass_ms"][1] / 1e3 / max(1, launches)
     out = {
         "metric": METRIC,
@@ -373,13 +431,12 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        # scores on BF16 MFMA (FP32 accumulation) for the screen, else FP32;
-        # decisions certified in FP32/FP64
         # products in BF16 (the split screen: high and low BF16 parts), FP32
-        # accumulation; FP64 decisions near ties
-        "dtype": "bf16" if bf16_screen else ("bf16x3-split" if split_screen else "f32"),
+        # accumulation; FP64 decisions near ties; "f32" for the FP32 kernels
+        "dtype": dtype_label,
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k,
+                   "precision": args.precision,
                    "subset_frac": w.subset_frac, "max_iter": w.max_iter, "tol": w.tol,
                    "passes": info["iters"], "m": info["m"],
                    "dist_evals_per_fit": info["dist_evals"],

@@ -92,6 +92,36 @@ typedef struct {
   double* centers64_out;       /* optional DEVICE k*d FP64 copy of the returned centers */
   double* J_hist;              /* optional HOST arrays of max_iter[0] + max_iter[1] entries: */
   double* shift_hist;          /*   J and shift of every pass, fast stage first */
+  /* Optional caller-provided DEVICE scratch (256-byte aligned).  With workspace
+     != NULL the call takes all its device memory from it and allocates none;
+     it returns KM_ENOMEM when workspace_bytes is below kmeans_workspace_bytes()
+     for the same sizes and options.  The library keeps nothing in it after the
+     call returns; calls that share one workspace must not overlap. */
+  void* workspace;
+  size_t workspace_bytes;
+  /* 1: scan all of X for NaN/Inf before any pass (one extra read of X), so bad
+     data fails before the fast stage; 0: each stage's statistics pass finds it
+     (the same KM_EINVAL, after the fast stage when the bad rows lie outside the
+     subset). */
+  int32_t check_finite;
+  /* Empty clusters.  0 (the paper is silent; the default): an empty cluster keeps
+     its center.  1: after the update of a pass that left clusters empty, the
+     lowest-index empty cluster takes as its new center the point farthest (FP64
+     squared distance) from its nearest updated center, lowest point index on
+     equal distances; that movement counts in the pass's largest movement.  One
+     cluster per pass (section 3 warns of blank clusters from small subsets). */
+  int32_t reseed;
+  /* Optional HOST per-pass trace in the form of Table 1 (section 5), fast stage
+     first, pass p of stage s at row max_iter[0]*s + p (rows past the passes
+     run are zero):
+       trace_centers: (max_iter[0] + max_iter[1]) * k * d FP64, the centers the
+                      pass starts from (a pass's new centers start the next pass
+                      of its stage, the fast stage's last ones start the slow
+                      stage, the slow stage's last ones are returned);
+       trace_counts:  (max_iter[0] + max_iter[1]) * k, the cluster sizes the
+                      pass found. */
+  double* trace_centers;
+  int64_t* trace_counts;
 } km_options;
 
 /*
@@ -113,7 +143,8 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
 /* Options equivalent to kmeans_fit(max_iter, tol) on FP32 data. */
 void kmeans_default_options(km_options* opt, int32_t max_iter, double tol);
 
-/* Device bytes kmeans_fit_ex allocates for these sizes (0 on invalid sizes). */
+/* Device bytes kmeans_fit_ex allocates for these sizes and options (0 on
+   invalid sizes): the smallest workspace_bytes a caller workspace may have. */
 size_t kmeans_workspace_bytes(int64_t n, int32_t d, int32_t k, double subset_frac,
                               const km_options* opt);
 
@@ -166,6 +197,20 @@ typedef struct {
 
 km_status kmeans_profile_begin(void);
 km_status kmeans_profile_end(km_prof* out);
+
+/*
+ * Measured roofline denominators (beside the datasheet peaks), timed with HIP
+ * events on `stream` (hipStream_t or NULL) after one untimed launch:
+ *   km_probe_stream_read: read `bytes` (>= 16) of the 16-byte aligned DEVICE
+ *     buffer `buf` `reps` times with 16-byte loads; *gbps = bytes read per
+ *     second / 1e9;
+ *   km_probe_mfma_bf16: two waves per SIMD on every CU, each `iters` rounds of
+ *     four independent 32x32x16 BF16 MFMAs (FP32 accumulation), no memory
+ *     traffic; *tflops = 2 * 32 * 32 * 16 flops per MFMA per second / 1e12.
+ */
+km_status km_probe_stream_read(const void* buf, size_t bytes, int32_t reps, double* gbps,
+                               void* stream);
+km_status km_probe_mfma_bf16(int32_t iters, double* tflops, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Many independent problems at once.  Each request is the two-stage method of
@@ -246,10 +291,16 @@ km_status km_server_create(const km_server_cfg* cfg, km_server** out);
    for the ticket. */
 km_status km_server_submit(km_server* srv, const km_request* req, uint64_t* ticket);
 /* Waits up to timeout_us (< 0: forever) for the ticket's result; KM_ETIMEOUT
-   leaves it pending, KM_ENOTFOUND for an unknown or already collected ticket. */
+   leaves it pending, KM_ENOTFOUND for an unknown or already collected ticket.
+   Admission goes by arrival order, except that a problem which does not fit
+   yet lets later ones that fit go first, at most 64 admission rounds in a
+   row; then the queue waits for it. */
 km_status km_server_wait(km_server* srv, uint64_t ticket, km_result* out, int64_t timeout_us);
 km_status km_server_stats(km_server* srv, km_server_counters* out);
-/* Stops the scheduler; unfinished problems complete with KM_ECANCELLED. */
+/* Stops the scheduler; unfinished problems (waiting or running) complete with
+   KM_ECANCELLED, and threads blocked in km_server_wait return that status.
+   Returns after every such thread has left km_server_wait; the handle is then
+   freed, so no call on it may start once destroy has begun. */
 km_status km_server_destroy(km_server* srv);
 
 /* Return the device memory the library keeps for reuse between calls. */

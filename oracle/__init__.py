@@ -7,7 +7,9 @@ which passage of the paper each part follows.
 
 Parity unpinned: nothing.  Every function is pinned by the CPU tests against
 published SplitMix64 outputs, brute-force enumeration of partitions, closed
-forms (k = 1, k = n, 1-D two-means) and invariants of Lloyd's method.
+forms (k = 1, k = n, 1-D two-means), invariants of Lloyd's method, and (for
+the per-pass trace and the empty-cluster variant) hand-built cases whose
+answers follow from the definitions.
 """
 from __future__ import annotations
 
@@ -66,6 +68,10 @@ def _load():
         lib.oracle_step.argtypes = [vp, i32, i64, i32, vp, i32, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_fit.argtypes = [vp, i32, i64, i32, i32, f64, u64, vp, vp, vp, i32, vp, vp,
                                    ctypes.POINTER(Info), vp, vp, vp, vp]
+        lib.oracle_step_ex.argtypes = [vp, i32, i64, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp,
+                                       vp]
+        lib.oracle_fit_ex.argtypes = [vp, i32, i64, i32, i32, f64, u64, vp, vp, vp, i32, i32, vp,
+                                      vp, ctypes.POINTER(Info), vp, vp, vp, vp, vp, vp, vp, vp]
         lib.oracle_set_threads.argtypes = [i32]
         lib.oracle_get_threads.restype = i32
         _lib = lib
@@ -131,8 +137,9 @@ class Step:
     empty: int
 
 
-def step(Y: np.ndarray, C: np.ndarray) -> Step:
-    """One Lloyd pass (assignment, J, update) from centers C."""
+def step(Y: np.ndarray, C: np.ndarray, reseed: bool = False) -> Step:
+    """One Lloyd pass (assignment, J, update) from centers C; with ``reseed`` the
+    lowest empty cluster moves to the farthest point (see the C source)."""
     Y = np.ascontiguousarray(Y)
     C = np.ascontiguousarray(C, dtype=np.float64)
     n, d = Y.shape
@@ -144,9 +151,9 @@ def step(Y: np.ndarray, C: np.ndarray) -> Step:
     J = ctypes.c_double()
     sh = ctypes.c_double()
     ne = ctypes.c_int32()
-    rc = _load().oracle_step(_c(Y), _xcode(Y), n, d, _c(C), k, _c(lab), _c(S), _c(N),
-                             ctypes.addressof(J), _c(Cn), ctypes.addressof(sh),
-                             ctypes.addressof(ne))
+    rc = _load().oracle_step_ex(_c(Y), _xcode(Y), n, d, _c(C), k, int(bool(reseed)), _c(lab),
+                                _c(S), _c(N), ctypes.addressof(J), _c(Cn), ctypes.addressof(sh),
+                                ctypes.addressof(ne))
     if rc:
         raise ValueError("oracle_step failed")
     return Step(lab, S, N, J.value, Cn, sh.value, ne.value)
@@ -159,11 +166,15 @@ class Fit:
     info: dict
     J_hist: tuple
     shift_hist: tuple
+    trace_centers: tuple = None   # per stage: (passes, k, d) centers each pass starts from
+    trace_counts: tuple = None    # per stage: (passes, k) cluster sizes each pass finds
 
 
 def fit(X: np.ndarray, k: int, subset_frac: float, seed: int, max_iter, tol,
-        init_centers: np.ndarray | None = None, skip_stage1: bool = False) -> Fit:
-    """The two-stage method.  ``max_iter`` / ``tol``: a number or a (fast, slow) pair."""
+        init_centers: np.ndarray | None = None, skip_stage1: bool = False,
+        reseed: bool = False, trace: bool = False) -> Fit:
+    """The two-stage method.  ``max_iter`` / ``tol``: a number or a (fast, slow) pair;
+    ``reseed``: the empty-cluster variant; ``trace``: per-pass centers and sizes."""
     X = np.ascontiguousarray(X)
     n, d = X.shape
     mi = np.array(max_iter if np.ndim(max_iter) else (max_iter, max_iter), np.int32)
@@ -177,15 +188,22 @@ def fit(X: np.ndarray, k: int, subset_frac: float, seed: int, max_iter, tol,
     if init_centers is not None:
         ic = np.ascontiguousarray(init_centers, dtype=np.float64)
         assert ic.shape == (k, d)
-    rc = _load().oracle_fit(_c(X), _xcode(X), n, d, k, subset_frac, seed, _c(mi), _c(tl),
-                            _c(ic) if ic is not None else None, int(skip_stage1), _c(C),
-                            _c(lab), ctypes.byref(info), _c(jh[0]), _c(sh[0]), _c(jh[1]),
-                            _c(sh[1]))
+    tc = [np.zeros((max(1, int(mi[s])), k, d), np.float64) if trace else None for s in range(2)]
+    tn = [np.zeros((max(1, int(mi[s])), k), np.int64) if trace else None for s in range(2)]
+    opt = lambda a: _c(a) if a is not None else None  # noqa: E731
+    rc = _load().oracle_fit_ex(_c(X), _xcode(X), n, d, k, subset_frac, seed, _c(mi), _c(tl),
+                               opt(ic), int(skip_stage1), int(bool(reseed)), _c(C), _c(lab),
+                               ctypes.byref(info), _c(jh[0]), _c(sh[0]), _c(jh[1]), _c(sh[1]),
+                               opt(tc[0]), opt(tn[0]), opt(tc[1]), opt(tn[1]))
     if rc:
         raise ValueError(f"oracle_fit failed ({rc})")
     it = info.iters
-    return Fit(C, lab, info.as_dict(), (jh[0][:it[0]], jh[1][:it[1]]),
-               (sh[0][:it[0]], sh[1][:it[1]]))
+    out = Fit(C, lab, info.as_dict(), (jh[0][:it[0]], jh[1][:it[1]]),
+              (sh[0][:it[0]], sh[1][:it[1]]))
+    if trace:
+        out.trace_centers = (tc[0][:it[0]], tc[1][:it[1]])
+        out.trace_counts = (tn[0][:it[0]], tn[1][:it[1]])
+    return out
 
 
 def set_threads(n: int) -> None:

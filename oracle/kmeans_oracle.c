@@ -28,7 +28,15 @@
  *    Algorithm): the k smallest keys, in key order;
  *  - slow stage: the whole data set starting from the fast stage's centers
  *    (Algorithm, "Use the whole dataset"; corollary of section 4.1);
- *  - output: labels and J over all points at the returned centers.
+ *  - output: labels and J over all points at the returned centers;
+ *  - optional variant for empty clusters (section 3 names blank clusters as
+ *    the risk of small subsets; the paper gives no rule): after the update of
+ *    a pass that left clusters empty, the lowest-index empty cluster takes as
+ *    its new center the point farthest from its nearest updated center (the
+ *    lowest point index among equally far points), and that movement joins the
+ *    pass's largest movement.  One cluster per pass;
+ *  - optional trace in the form of Table 1 (section 5): for every pass, the
+ *    centers it starts from and the number of points of each cluster.
  */
 #include "kmeans_oracle.h"
 
@@ -161,9 +169,47 @@ int oracle_assign(const void* X, int32_t dtype, int64_t n, int32_t d, const doub
 }
 
 /* ---- one Lloyd pass -------------------------------------------------------- */
+/* Re-seeding of one empty cluster j: the point farthest from its nearest
+   center of Cn (squared distance, direct form; lowest index on ties) becomes
+   center j.  Returns the center's movement. */
+static double reseed_farthest(const void* Y, int32_t dtype, int64_t n, int32_t d, double* Cn,
+                              int32_t k, int32_t j) {
+  double far = -1.0;
+  int64_t fi = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double m = INFINITY;
+    for (int32_t l = 0; l < k; ++l) {
+      double D = 0.0;
+      for (int32_t t = 0; t < d; ++t) {
+        double diff = xval(Y, dtype, i * d + t) - Cn[(int64_t)l * d + t];
+        D += diff * diff;
+      }
+      if (D < m) m = D;
+    }
+    if (m > far) {  /* strictly farther: the lowest index wins among equals */
+      far = m;
+      fi = i;
+    }
+  }
+  double mv = 0.0;
+  for (int32_t t = 0; t < d; ++t) {
+    double x = xval(Y, dtype, fi * d + t);
+    double diff = x - Cn[(int64_t)j * d + t];
+    mv += diff * diff;
+    Cn[(int64_t)j * d + t] = x;
+  }
+  return sqrt(mv);
+}
+
 int oracle_step(const void* Y, int32_t dtype, int64_t n, int32_t d, const double* C, int32_t k,
                 int32_t* labels, double* S, int64_t* N, double* J, double* Cnew, double* shift,
                 int32_t* empty) {
+  return oracle_step_ex(Y, dtype, n, d, C, k, 0, labels, S, N, J, Cnew, shift, empty);
+}
+
+int oracle_step_ex(const void* Y, int32_t dtype, int64_t n, int32_t d, const double* C,
+                   int32_t k, int32_t reseed, int32_t* labels, double* S, int64_t* N, double* J,
+                   double* Cnew, double* shift, int32_t* empty) {
   if (!Y || !C || n < 1 || d < 1 || k < 1) return 1;
   int32_t* lab = labels ? labels : (int32_t*)malloc((size_t)n * sizeof(int32_t));
   double* D1 = (double*)malloc((size_t)n * sizeof(double));
@@ -199,6 +245,12 @@ int oracle_step(const void* Y, int32_t dtype, int64_t n, int32_t d, const double
     double mvr = sqrt(mv);
     if (mvr > mx) mx = mvr;
   }
+  if (reseed && ne > 0) {
+    int32_t je = 0;
+    while (Nl[je] != 0) ++je;
+    double mvr = reseed_farthest(Y, dtype, n, d, Cn, k, je);
+    if (mvr > mx) mx = mvr;
+  }
   if (J) *J = Jsum;
   if (shift) *shift = mx;
   if (empty) *empty = ne;
@@ -212,15 +264,19 @@ int oracle_step(const void* Y, int32_t dtype, int64_t n, int32_t d, const double
 
 /* One stage: passes until the largest center movement is below tol or max_iter. */
 static int run_stage(const void* Y, int32_t dtype, int64_t n, int32_t d, int32_t k, double* C,
-                     int32_t max_iter, double tol, int32_t* iters, int32_t* converged,
-                     int32_t* empty, double* Jlast, double* shlast, double* Jh, double* Sh) {
+                     int32_t max_iter, double tol, int32_t reseed, int32_t* iters,
+                     int32_t* converged, int32_t* empty, double* Jlast, double* shlast,
+                     double* Jh, double* Sh, double* Tc, int64_t* Tn) {
   double* Cn = (double*)malloc((size_t)k * d * sizeof(double));
-  if (!Cn) return 2;
+  int64_t* Nv = (int64_t*)malloc((size_t)k * sizeof(int64_t));
+  if (!Cn || !Nv) return 2;
   int32_t t = 0, conv = 0, ne = 0;
   double Jv = 0.0, sh = 0.0;
   while (t < max_iter) {
-    int rc = oracle_step(Y, dtype, n, d, C, k, NULL, NULL, NULL, &Jv, Cn, &sh, &ne);
-    if (rc) { free(Cn); return rc; }
+    if (Tc) memcpy(Tc + (size_t)t * k * d, C, (size_t)k * d * sizeof(double));
+    int rc = oracle_step_ex(Y, dtype, n, d, C, k, reseed, NULL, NULL, Nv, &Jv, Cn, &sh, &ne);
+    if (rc) { free(Cn); free(Nv); return rc; }
+    if (Tn) memcpy(Tn + (size_t)t * k, Nv, (size_t)k * sizeof(int64_t));
     memcpy(C, Cn, (size_t)k * d * sizeof(double));
     if (Jh) Jh[t] = Jv;
     if (Sh) Sh[t] = sh;
@@ -233,6 +289,7 @@ static int run_stage(const void* Y, int32_t dtype, int64_t n, int32_t d, int32_t
   *Jlast = Jv;
   *shlast = sh;
   free(Cn);
+  free(Nv);
   return 0;
 }
 
@@ -241,6 +298,17 @@ int oracle_fit(const void* X, int32_t dtype, int64_t n, int32_t d, int32_t k, do
                const double* init_centers, int32_t skip_stage1, double* centers_out,
                int32_t* labels_out, oracle_info* info, double* J_hist0, double* shift_hist0,
                double* J_hist1, double* shift_hist1) {
+  return oracle_fit_ex(X, dtype, n, d, k, subset_frac, seed, max_iter, tol, init_centers,
+                       skip_stage1, 0, centers_out, labels_out, info, J_hist0, shift_hist0,
+                       J_hist1, shift_hist1, NULL, NULL, NULL, NULL);
+}
+
+int oracle_fit_ex(const void* X, int32_t dtype, int64_t n, int32_t d, int32_t k,
+                  double subset_frac, uint64_t seed, const int32_t* max_iter, const double* tol,
+                  const double* init_centers, int32_t skip_stage1, int32_t reseed,
+                  double* centers_out, int32_t* labels_out, oracle_info* info, double* J_hist0,
+                  double* shift_hist0, double* J_hist1, double* shift_hist1, double* trace_c0,
+                  int64_t* trace_n0, double* trace_c1, int64_t* trace_n1) {
   if (!X || !max_iter || !tol || !centers_out || !info) return 1;
   if (n < 1 || d < 1 || k < 1 || k > n || dtype < 0 || dtype > 2) return 1;
   if (!(subset_frac > 0.0 && subset_frac <= 1.0)) return 1;
@@ -265,16 +333,18 @@ int oracle_fit(const void* X, int32_t dtype, int64_t n, int32_t d, int32_t k, do
     if (!Y) return 2;
     for (int64_t r = 0; r < m; ++r)
       for (int32_t t = 0; t < d; ++t) Y[r * d + t] = xval(X, dtype, sub[r] * d + t);
-    rc = run_stage(Y, 2, m, d, k, C, max_iter[0], tol[0], &info->iters[0], &info->converged[0],
-                   &info->empty[0], &Jv, &sh, J_hist0, shift_hist0);
+    rc = run_stage(Y, 2, m, d, k, C, max_iter[0], tol[0], reseed, &info->iters[0],
+                   &info->converged[0], &info->empty[0], &Jv, &sh, J_hist0, shift_hist0,
+                   trace_c0, trace_n0);
     free(Y);
     if (rc) return rc;
     info->J_stage1 = Jv;
     info->shift[0] = sh;
   }
   /* slow stage on the whole data, from the fast stage's centers */
-  rc = run_stage(X, dtype, n, d, k, C, max_iter[1], tol[1], &info->iters[1], &info->converged[1],
-                 &info->empty[1], &Jv, &sh, J_hist1, shift_hist1);
+  rc = run_stage(X, dtype, n, d, k, C, max_iter[1], tol[1], reseed, &info->iters[1],
+                 &info->converged[1], &info->empty[1], &Jv, &sh, J_hist1, shift_hist1, trace_c1,
+                 trace_n1);
   if (rc) return rc;
   info->shift[1] = sh;
   /* labels and J at the returned centers */

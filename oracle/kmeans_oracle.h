@@ -61,6 +61,24 @@ int oracle_fit(const void* X, int32_t dtype, int64_t n, int32_t d, int32_t k, do
                int32_t* labels_out, oracle_info* info, double* J_hist0, double* shift_hist0,
                double* J_hist1, double* shift_hist1);
 
+/* oracle_step with the optional empty-cluster re-seeding (reseed = 1): after
+   the update, the lowest-index empty cluster moves to the point farthest from
+   its nearest updated center (lowest index on ties); its movement counts in
+   shift.  reseed = 0 is oracle_step. */
+int oracle_step_ex(const void* Y, int32_t dtype, int64_t n, int32_t d, const double* C,
+                   int32_t k, int32_t reseed, int32_t* labels, double* S, int64_t* N, double* J,
+                   double* Cnew, double* shift, int32_t* empty);
+
+/* oracle_fit with re-seeding and the optional per-pass trace of each stage:
+   trace_c<s> (max_iter[s] * k * d) receives the centers every pass starts from,
+   trace_n<s> (max_iter[s] * k) the cluster sizes the pass finds. */
+int oracle_fit_ex(const void* X, int32_t dtype, int64_t n, int32_t d, int32_t k,
+                  double subset_frac, uint64_t seed, const int32_t* max_iter, const double* tol,
+                  const double* init_centers, int32_t skip_stage1, int32_t reseed,
+                  double* centers_out, int32_t* labels_out, oracle_info* info, double* J_hist0,
+                  double* shift_hist0, double* J_hist1, double* shift_hist1, double* trace_c0,
+                  int64_t* trace_n0, double* trace_c1, int64_t* trace_n1);
+
 void oracle_set_threads(int32_t nthreads);
 int32_t oracle_get_threads(void);
 

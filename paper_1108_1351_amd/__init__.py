@@ -25,7 +25,7 @@ EXPORTS = ("kmeans_fit", "kmeans_fit_ex", "kmeans_default_options", "kmeans_work
            "km_sample", "km_step", "km_assign", "kmeans_last_error", "kmeans_profile_begin",
            "kmeans_profile_end", "kmeans_release_memory", "kmeans_fit_batch", "km_tune_query",
            "km_server_create", "km_server_submit", "km_server_wait", "km_server_stats",
-           "km_server_destroy")
+           "km_server_destroy", "km_probe_stream_read", "km_probe_mfma_bf16")
 
 
 class KMeansError(RuntimeError):
@@ -54,7 +54,10 @@ class km_options(ctypes.Structure):
                 ("max_iter", ctypes.c_int32 * 2), ("tol", ctypes.c_double * 2),
                 ("init_centers", ctypes.c_void_p), ("skip_stage1", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("centers64_out", ctypes.c_void_p),
-                ("J_hist", ctypes.c_void_p), ("shift_hist", ctypes.c_void_p)]
+                ("J_hist", ctypes.c_void_p), ("shift_hist", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("check_finite", ctypes.c_int32), ("reseed", ctypes.c_int32),
+                ("trace_centers", ctypes.c_void_p), ("trace_counts", ctypes.c_void_p)]
 
 
 class km_prof(ctypes.Structure):
@@ -135,10 +138,13 @@ def load():
     lib.km_server_wait.argtypes = [vp, u64, P(km_result), i64]
     lib.km_server_stats.argtypes = [vp, P(km_server_counters)]
     lib.km_server_destroy.argtypes = [vp]
+    lib.km_probe_stream_read.argtypes = [vp, ctypes.c_size_t, i32, P(f64), vp]
+    lib.km_probe_mfma_bf16.argtypes = [i32, P(f64), vp]
     for name in ("kmeans_fit", "kmeans_fit_ex", "km_sample", "km_step", "km_assign",
                  "kmeans_profile_begin", "kmeans_profile_end", "kmeans_release_memory",
                  "kmeans_fit_batch", "km_tune_query", "km_server_create", "km_server_submit",
-                 "km_server_wait", "km_server_stats", "km_server_destroy"):
+                 "km_server_wait", "km_server_stats", "km_server_destroy",
+                 "km_probe_stream_read", "km_probe_mfma_bf16"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -196,16 +202,10 @@ def kmeans_fit(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter:
     return C, L, info.as_dict()
 
 
-def kmeans_fit_ex(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter=50,
-                  tol=1e-4, *, precision: str = "auto", init_centers=None,
-                  skip_stage1: bool = False, labels: bool = True, centers64: bool = False,
-                  history: bool = False, stream=None):
-    """Per-stage limits, FP32 or BF16 data, resume point (C: kmeans_fit_ex).
-
-    Returns (centers FP32, labels or None, info dict); the dict also carries
-    ``centers64`` (device FP64) and ``J_hist`` / ``shift_hist`` when requested.
-    """
-    lib = load()
+def _options(X, k, max_iter, tol, precision, init_centers, skip_stage1, stream, workspace,
+             check_finite, reseed):
+    """A km_options for kmeans_fit_ex and its no-allocation variant (plus the host
+    arrays that must outlive the call)."""
     n, d = X.shape
     opt = km_options()
     mi, tl = _pair(max_iter), _pair(tol)
@@ -215,13 +215,45 @@ def kmeans_fit_ex(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_it
     opt.tol[0], opt.tol[1] = float(tl[0]), float(tl[1])
     opt.skip_stage1 = int(bool(skip_stage1))
     opt.stream = _stream(stream)
-    ic = None
+    opt.check_finite = int(bool(check_finite))
+    opt.reseed = int(bool(reseed))
+    keep = []
     if init_centers is not None:
         import numpy as np
         ic = np.ascontiguousarray(init_centers, dtype=np.float64)
         if ic.shape != (k, d):
             raise ValueError("init_centers must have shape (k, d)")
         opt.init_centers = ic.ctypes.data
+        keep.append(ic)
+    if workspace is not None:
+        opt.workspace = _dev(workspace, "workspace")
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    return opt, keep
+
+
+def kmeans_fit_ex(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter=50,
+                  tol=1e-4, *, precision: str = "auto", init_centers=None,
+                  skip_stage1: bool = False, labels: bool = True, centers64: bool = False,
+                  history: bool = False, stream=None, workspace: torch.Tensor | None = None,
+                  check_finite: bool = False, reseed: bool = False, trace: bool = False):
+    """Per-stage limits, FP32 or BF16 data, resume point (C: kmeans_fit_ex).
+
+    Returns (centers FP32, labels or None, info dict); the dict also carries
+    ``centers64`` (device FP64), ``J_hist`` / ``shift_hist`` and (``trace``) the
+    per-pass ``trace_centers`` / ``trace_counts`` of each stage when requested.
+    ``workspace``: a device tensor the call takes its scratch from
+    (kmeans_workspace_bytes); ``reseed``: empty-cluster re-seeding.
+    """
+    lib = load()
+    opt, keep = _options(X, k, max_iter, tol, precision, init_centers, skip_stage1, stream,
+                         workspace, check_finite, reseed)
+    return _fit_call(lib.kmeans_fit_ex, X, k, subset_frac, seed, opt, labels, centers64,
+                     history, trace)
+
+
+def _fit_call(entry, X, k, subset_frac, seed, opt, labels, centers64, history, trace):
+    n, d = X.shape
+    mi = (opt.max_iter[0], opt.max_iter[1])
     C = torch.empty((k, d), dtype=torch.float32, device=X.device)
     L = torch.empty(n, dtype=torch.int32, device=X.device) if labels else None
     C64 = torch.empty((k, d), dtype=torch.float64, device=X.device) if centers64 else None
@@ -231,29 +263,43 @@ def kmeans_fit_ex(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_it
         jh = np.zeros(int(mi[0]) + int(mi[1]), np.float64)
         sh = np.zeros_like(jh)
         opt.J_hist, opt.shift_hist = jh.ctypes.data, sh.ctypes.data
+    if trace:
+        import numpy as np
+        tc = np.zeros((int(mi[0]) + int(mi[1]), k, d), np.float64)
+        tn = np.zeros((int(mi[0]) + int(mi[1]), k), np.int64)
+        opt.trace_centers, opt.trace_counts = tc.ctypes.data, tn.ctypes.data
     info = km_info()
-    rc = lib.kmeans_fit_ex(_dev(X, "X"), n, d, k, subset_frac, seed, ctypes.byref(opt),
-                           C.data_ptr(), L.data_ptr() if L is not None else None,
-                           ctypes.byref(info))
+    rc = entry(_dev(X, "X"), n, d, k, subset_frac, seed, ctypes.byref(opt), C.data_ptr(),
+               L.data_ptr() if L is not None else None, ctypes.byref(info))
     _check(rc)
     out = info.as_dict()
     if C64 is not None:
         out["centers64"] = C64
+    it = out["iters"]
     if history:
-        it = out["iters"]
         out["J_hist"] = (jh[:it[0]].copy(), jh[int(mi[0]):int(mi[0]) + it[1]].copy())
         out["shift_hist"] = (sh[:it[0]].copy(), sh[int(mi[0]):int(mi[0]) + it[1]].copy())
+    if trace:
+        out["trace_centers"] = (tc[:it[0]].copy(), tc[int(mi[0]):int(mi[0]) + it[1]].copy())
+        out["trace_counts"] = (tn[:it[0]].copy(), tn[int(mi[0]):int(mi[0]) + it[1]].copy())
     return C, L, out
 
 
 def kmeans_workspace_bytes(n: int, d: int, k: int, subset_frac: float, max_iter=50,
-                           dtype=torch.float32, skip_stage1: bool = False) -> int:
+                           dtype=torch.float32, skip_stage1: bool = False,
+                           precision: str = "auto", reseed: bool = False,
+                           trace: bool = False) -> int:
+    """Device bytes a fit with these sizes and options takes (C: kmeans_workspace_bytes)."""
     opt = km_options()
     load().kmeans_default_options(ctypes.byref(opt), 1, 0.0)
     mi = _pair(max_iter)
     opt.max_iter[0], opt.max_iter[1] = int(mi[0]), int(mi[1])
     opt.dtype = KM_F32 if dtype == torch.float32 else KM_BF16
+    opt.precision = PRECISION[precision]
     opt.skip_stage1 = int(skip_stage1)
+    opt.reseed = int(bool(reseed))
+    if trace:  # only whether a trace is asked for matters to the size
+        opt.trace_counts = 1
     return int(load().kmeans_workspace_bytes(n, d, k, subset_frac, ctypes.byref(opt)))
 
 
@@ -313,6 +359,21 @@ def kmeans_profile_end() -> dict:
 
 def kmeans_release_memory() -> None:
     _check(load().kmeans_release_memory())
+
+
+def km_probe_stream_read(buf: torch.Tensor, reps: int = 5, stream=None) -> float:
+    """Measured device-memory read bandwidth (GB/s) over the bytes of ``buf``."""
+    v = ctypes.c_double()
+    _check(load().km_probe_stream_read(_dev(buf, "buf"), buf.numel() * buf.element_size(),
+                                       reps, ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def km_probe_mfma_bf16(iters: int = 20000, stream=None) -> float:
+    """Measured dense BF16 MFMA rate (TFLOP/s) of a loop with no memory traffic."""
+    v = ctypes.c_double()
+    _check(load().km_probe_mfma_bf16(iters, ctypes.byref(v), _stream(stream)))
+    return v.value
 
 
 def _request(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter, tol,

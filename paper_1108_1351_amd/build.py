@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkmeans_mi355x.so")
-SOURCES = ["kernels.hip", "driver.hip", "serve.hip"]
+# every HIP source of csrc/ goes into the one library
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
 ARCH = os.environ.get("KM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

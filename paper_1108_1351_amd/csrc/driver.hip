@@ -29,7 +29,7 @@ namespace {
 struct Layout {
   size_t sel, hist, blk, sub, init_sel, init_key, xs, c64, cw, cn, cnorm, shiftj, emptyj, st,
       jh, sh, slots, jslots, cb16, cnb, queue, qthr, jpart, upart, labels, perm, scnt, stot,
-      rstart;
+      rstart, tc, tn, fpart, fidx, rqc;
   size_t bytes;
   bool labels_ws;
 };
@@ -42,6 +42,7 @@ struct Sizes {
   int32_t hist_len;
   PassPlan p1, p2;
   bool need_labels_ws;
+  bool trace, reseed;
 };
 
 // per-block partials: the BF16 screen's re-screen kernel has a second set
@@ -99,8 +100,9 @@ Layout make_layout(const Sizes& z) {
   L.jslots = c.take<long long>((size_t)kSlots * 2);
   L.cb16 = c.take<uint16_t>(any_copy16(z) ? (size_t)bf16_rows(z.k) * 16 * ks_max(z) : 0);
   L.cnb = c.take<float>((size_t)bf16_rows(z.k));
-  L.queue = c.take<int32_t>(any_bf16(z) ? (size_t)z.n : 0);
+  L.queue = c.take<uint32_t>(any_bf16(z) ? (size_t)z.n : 0);
   L.qthr = c.take<float>(any_bf16(z) ? (size_t)z.n : 0);
+  L.rqc = c.take<int4>(any_bf16(z) ? (size_t)z.n : 0);
   L.jpart = c.take<double>((size_t)blocks_max(z));
   L.upart = c.take<long long>((size_t)blocks_max(z) * 2);
   L.labels_ws = z.need_labels_ws;
@@ -110,6 +112,11 @@ Layout make_layout(const Sizes& z) {
   L.scnt = c.take<long long>(so.cnt);
   L.stot = c.take<long long>(so.tiles);
   L.rstart = c.take<long long>(so.starts);
+  // per-pass trace (device copy, brought back at the end) and re-seeding partials
+  L.tc = c.take<double>(z.trace ? (size_t)z.hist_len * z.k * z.d : 0);
+  L.tn = c.take<long long>(z.trace ? (size_t)z.hist_len * z.k : 0);
+  L.fpart = c.take<double>(z.reseed ? (size_t)kFarBlocks : 0);
+  L.fidx = c.take<long long>(z.reseed ? (size_t)kFarBlocks : 0);
   L.bytes = c.off;
   return L;
 }
@@ -178,15 +185,17 @@ struct StageResult {
   int64_t uncertain = 0, pairs = 0;
 };
 
-// One stage's Lloyd loop on `rows` rows of Y.
+// One stage's Lloyd loop on `rows` rows of Y.  noalloc: the host reads the
+// pass state into its own (pageable) memory after each chunk and waits for
+// it, with no pinned buffer, event or profiler event to create.
 km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double tol,
-                    hipStream_t s, StageResult* out, int stage) {
+                    hipStream_t s, StageResult* out, int stage, int reseed, bool noalloc) {
   km_status rc = KM_OK;
   PassState hs;
   int32_t launched = 0, chunk = 2;
   const int64_t rows = b.n;
-  const bool prof = prof_on();
-  StageSync* ss = stage_sync();
+  const bool prof = !noalloc && prof_on();
+  StageSync* ss = noalloc ? nullptr : stage_sync();
   int slot = 0, in_flight = 0;
   auto drain = [&]() {  // the copies still in flight land before the buffers are reused
     for (; in_flight > 0; --in_flight) {
@@ -194,13 +203,14 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
       (void)hipEventSynchronize(ss->ev[old]);
     }
   };
-  if (!ss) return fail(KM_EDEVICE, "pinned pass-state buffer or events unavailable");
+  if (!ss && !noalloc) return fail(KM_EDEVICE, "pinned pass-state buffer or events unavailable");
   std::vector<hipEvent_t> ev;
   if (prof)
     for (int32_t i = 0; i < 3 * max_iter; ++i) ev.push_back(take_event());
   HIP_TRY(stage_reset(b.st, s));
   HIP_TRY(row_stats(b.X, b.dtype, rows, b.d, wants_norms(plan), b.st, s));
-  HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, b.d, plan.fused ? 0 : plan.pg, s));
+  HIP_TRY(stage_begin(b.st, max_iter, tol, rows, b.cnorm, b.k, b.d, plan.fused ? 0 : plan.pg, s,
+                      reseed));
   if (copy16(plan)) HIP_TRY(prep_bf16(b.c64, b.k, b.d, plan.ks * 16, b.st, b.cb16, b.cnB, s));
   HIP_TRY(zero_i64(b.slots, (int64_t)kSlots * b.k * (b.d + 1), s));
   HIP_TRY(zero_i64(b.jslots, (int64_t)kSlots * 2, s));
@@ -221,6 +231,16 @@ km_status run_stage(PassBufs b, const PassPlan& plan, int32_t max_iter, double t
       }
       launched += q;
       chunk = std::min(chunk * 2, 16);
+      if (noalloc) {
+        HIP_TRY(hipMemcpyAsync(&hs, b.st, sizeof(PassState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hs.nonfinite) {
+          rc = fail(KM_EINVAL, "X contains NaN or Inf");
+          goto done;
+        }
+        if (hs.done || launched >= max_iter) break;
+        continue;
+      }
       HIP_TRY(hipMemcpyAsync(&ss->h[slot], b.st, sizeof(PassState), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipEventRecord(ss->ev[slot], s));
       slot ^= 1;
@@ -342,6 +362,9 @@ static bool fit_sizes(int64_t n, int32_t d, int32_t k, double f, const km_option
   z->p1 = plan_pass(z->m, d, k, dt, (int)opt->precision, lds, device_cus());
   z->p2 = plan_pass(n, d, k, dt, (int)opt->precision, lds, device_cus());
   z->need_labels_ws = !labels_given && ((z->stage1 && !z->p1.fused) || !z->p2.fused);
+  z->trace = opt->trace_centers || opt->trace_counts;
+  z->reseed = opt->reseed != 0;
+  if (opt->reseed != 0 && opt->reseed != 1) return !fail(KM_EINVAL, "reseed must be 0 or 1");
   if (!z->p2.fused && n > (int64_t)UINT32_MAX)
     return !fail(KM_EINVAL, "n = %lld rows need the sorted update, which takes n < 2^32",
                  (long long)n);
@@ -361,10 +384,13 @@ size_t kmeans_workspace_bytes(int64_t n, int32_t d, int32_t k, double subset_fra
   return make_layout(z).bytes;
 }
 
-km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double subset_frac,
-                        uint64_t seed, const km_options* opt, float* centers_out,
-                        int32_t* labels_out, km_info* info) {
-  g_err.clear();
+}  // extern "C"
+
+namespace km {
+
+km_status fit_impl(const void* X, int64_t n, int32_t d, int32_t k, double subset_frac,
+                   uint64_t seed, const km_options* opt, float* centers_out, int32_t* labels_out,
+                   km_info* info, bool noalloc) {
   if (!opt) return fail(KM_EINVAL, "opt must not be NULL");
   if (!X || !centers_out) return fail(KM_EINVAL, "X and centers_out must not be NULL");
   Sizes z;
@@ -374,8 +400,18 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
       if (!std::isfinite(opt->init_centers[e])) return fail(KM_EINVAL, "init_centers not finite");
   hipStream_t s = (hipStream_t)opt->stream;
   const Layout L = make_layout(z);
+  if (opt->workspace) {
+    // a caller workspace must hold what kmeans_workspace_bytes() asks for (sized
+    // without labels_out), whatever this call's own layout needs
+    Sizes zmax;
+    (void)fit_sizes(n, d, k, subset_frac, opt, false, &zmax);
+    const size_t need = make_layout(zmax).bytes;
+    if (opt->workspace_bytes < need)
+      return fail(KM_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed",
+                  opt->workspace_bytes, need);
+  }
   DevMem mem;
-  km_status rc = mem.get(L.bytes, nullptr, 0, s);
+  km_status rc = mem.get(L.bytes, opt->workspace, opt->workspace_bytes, s);
   if (rc != KM_OK) return rc;
   void* base = mem.ptr;
   SelState* sel = at<SelState>(base, L.sel);
@@ -406,8 +442,9 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
   b.jslots = at<long long>(base, L.jslots);
   b.cb16 = at<uint16_t>(base, L.cb16);
   b.cnB = at<float>(base, L.cnb);
-  b.queue = at<int32_t>(base, L.queue);
+  b.queue = at<uint32_t>(base, L.queue);
   b.qthr = at<float>(base, L.qthr);
+  b.rq_c = at<int4>(base, L.rqc);
   b.Jpart = at<double>(base, L.jpart);
   b.upart = at<long long>(base, L.upart);
   b.perm = at<uint32_t>(base, L.perm);
@@ -415,6 +452,21 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
   b.stot = at<long long>(base, L.stot);
   b.rstart = at<long long>(base, L.rstart);
   b.st = st;
+  if (z.reseed) {
+    b.fpart = at<double>(base, L.fpart);
+    b.fidx = at<long long>(base, L.fidx);
+  }
+  if (opt->check_finite) {
+    // all of X, before any pass: the same scan the stage statistics make
+    HIP_TRY(stage_reset(st, s));
+    HIP_TRY(row_stats(X, dt, n, d, false, st, s));
+    HIP_TRY(hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs.maxabs_bits >= 0x7f800000u) {
+      rc = fail(KM_EINVAL, "X contains NaN or Inf");
+      goto done;
+    }
+  }
   HIP_TRY(hipMemsetAsync(hist, 0, sizeof(unsigned long long) * kSelBins, s));
 
   // ---- fast-stage subset and initial centers ("%per of S_n", "Select X_c")
@@ -449,7 +501,11 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
     b1.labels = z.p1.fused ? nullptr : lab_scratch;
     b1.J_hist = at<double>(base, L.jh);
     b1.shift_hist = at<double>(base, L.sh);
-    rc = run_stage(b1, z.p1, opt->max_iter[0], opt->tol[0], s, &r1, 0);
+    if (z.trace) {
+      b1.trace_c = at<double>(base, L.tc);
+      b1.trace_n = at<long long>(base, L.tn);
+    }
+    rc = run_stage(b1, z.p1, opt->max_iter[0], opt->tol[0], s, &r1, 0, opt->reseed, noalloc);
     if (rc != KM_OK) goto done;
   }
   t2 = now_s();
@@ -462,7 +518,11 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
     b2.labels = z.p2.fused ? nullptr : lab_scratch;
     b2.J_hist = at<double>(base, L.jh) + opt->max_iter[0];
     b2.shift_hist = at<double>(base, L.sh) + opt->max_iter[0];
-    rc = run_stage(b2, z.p2, opt->max_iter[1], opt->tol[1], s, &r2, 1);
+    if (z.trace) {
+      b2.trace_c = at<double>(base, L.tc) + (size_t)opt->max_iter[0] * k * d;
+      b2.trace_n = at<long long>(base, L.tn) + (size_t)opt->max_iter[0] * k;
+    }
+    rc = run_stage(b2, z.p2, opt->max_iter[1], opt->tol[1], s, &r2, 1, opt->reseed, noalloc);
     if (rc != KM_OK) goto done;
     // ---- labels and J at the returned centers
     b2.labels = z.p2.fused ? labels_out : lab_scratch;
@@ -477,9 +537,32 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(shh.data(), at<double>(base, L.sh), sizeof(double) * z.hist_len,
                          hipMemcpyDeviceToHost, s));
+  if (z.trace) {
+    // only the rows of passes that ran hold data; the rest are zeroed
+    const int run[2] = {r1.iters, r2.iters};
+    const size_t kd = (size_t)k * d;
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const size_t off = s2 == 0 ? 0 : (size_t)opt->max_iter[0];
+      const size_t lim = (size_t)opt->max_iter[s2];
+      if (opt->trace_centers) {
+        if (run[s2] > 0)
+          HIP_TRY(hipMemcpyAsync(opt->trace_centers + off * kd, at<double>(base, L.tc) + off * kd,
+                                 sizeof(double) * kd * run[s2], hipMemcpyDeviceToHost, s));
+        memset(opt->trace_centers + (off + run[s2]) * kd, 0,
+               sizeof(double) * kd * (lim - (size_t)run[s2]));
+      }
+      if (opt->trace_counts) {
+        if (run[s2] > 0)
+          HIP_TRY(hipMemcpyAsync(opt->trace_counts + off * k, at<long long>(base, L.tn) + off * k,
+                                 sizeof(int64_t) * k * run[s2], hipMemcpyDeviceToHost, s));
+        memset(opt->trace_counts + (off + run[s2]) * k, 0,
+               sizeof(int64_t) * k * (lim - (size_t)run[s2]));
+      }
+    }
+  }
   HIP_TRY(hipStreamSynchronize(s));
   t3 = now_s();
-  if (prof_on()) {
+  if (!noalloc && prof_on()) {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.acc.fits += 1;
   }
@@ -517,6 +600,17 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
 done:
   if (rc != KM_OK) (void)hipStreamSynchronize(s);
   return rc;
+}
+
+}  // namespace km
+
+extern "C" {
+
+km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double subset_frac,
+                        uint64_t seed, const km_options* opt, float* centers_out,
+                        int32_t* labels_out, km_info* info) {
+  g_err.clear();
+  return fit_impl(X, n, d, k, subset_frac, seed, opt, centers_out, labels_out, info, false);
 }
 
 km_status kmeans_fit(const float* X, int64_t n, int32_t d, int32_t k, double subset_frac,
@@ -581,8 +675,9 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
                o_st = c.take<PassState>(1), o_slots = c.take<long long>((size_t)kSlots * C_),
                o_qs = c.take<long long>((size_t)kSlots * 2),
                o_cb = c.take<uint16_t>(copy16(p) ? (size_t)bf16_rows(k) * 16 * p.ks : 0),
-               o_cnb = c.take<float>((size_t)bf16_rows(k)), o_q = c.take<int32_t>(p.bf16 ? (size_t)n : 0),
+               o_cnb = c.take<float>((size_t)bf16_rows(k)), o_q = c.take<uint32_t>(p.bf16 ? (size_t)n : 0),
                o_qt = c.take<float>(p.bf16 ? (size_t)n : 0),
+               o_rqc = c.take<int4>(p.bf16 ? (size_t)n : 0),
                o_jp = c.take<double>((size_t)p.blocks * 2),
                o_up = c.take<long long>((size_t)p.blocks * 4),
                o_lab = c.take<int32_t>(lab_ws ? (size_t)n : 0);
@@ -610,8 +705,9 @@ static km_status one_pass(const void* X, km_dtype dtype, int64_t n, int32_t d, c
   b.jslots = at<long long>(base, o_qs);
   b.cb16 = at<uint16_t>(base, o_cb);
   b.cnB = at<float>(base, o_cnb);
-  b.queue = at<int32_t>(base, o_q);
+  b.queue = at<uint32_t>(base, o_q);
   b.qthr = at<float>(base, o_qt);
+  b.rq_c = at<int4>(base, o_rqc);
   b.Jpart = at<double>(base, o_jp);
   b.upart = at<long long>(base, o_up);
   b.labels = labels ? labels : (lab_ws ? at<int32_t>(base, o_lab) : nullptr);

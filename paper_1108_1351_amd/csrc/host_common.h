@@ -168,5 +168,10 @@ struct DevMem {
   ~DevMem() { release(); }
 };
 
+// The two-stage fit behind kmeans_fit_ex (driver.hip).  noalloc: the device
+// memory is opt->workspace and the call creates no pinned buffer or event.
+km_status fit_impl(const void* X, int64_t n, int32_t d, int32_t k, double subset_frac,
+                   uint64_t seed, const km_options* opt, float* centers_out, int32_t* labels_out,
+                   km_info* info, bool noalloc);
 
 }  // namespace km

@@ -21,6 +21,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "km_internal.h"
 
@@ -331,6 +332,7 @@ __global__ void k_stage_reset(PassState* st) {
   st->ticket = 0u;
   st->dcn_bits = 0u;
   st->done = 0;
+  st->reseed_j = -1;
 }
 
 // Rounding error of one BF16 entry of the screen's center copy: the stored
@@ -519,7 +521,8 @@ __device__ __forceinline__ int ceil_log2(int64_t v) {
 __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
                                                      int32_t max_iter, double tol, int64_t rows,
                                                      const double* __restrict__ cnorm,
-                                                     int32_t k, int32_t d_, int64_t pg) {
+                                                     int32_t k, int32_t d_, int64_t pg,
+                                                     int reseed) {
   __shared__ double red[256];
   double m = 0.0;
   for (int j = threadIdx.x; j < k; j += 256) m = fmax(m, cnorm[j]);
@@ -559,10 +562,13 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
     st->FJ = FJ;
     // BF16 screen offset: every score ||c||^2 + B - 2 x.c stays positive, also
     // after the screen's rounding (at most 2^-7 ||x|| ||c|| from BF16 operands
-    // and (d+8) 2^-24 of the magnitudes from FP32 accumulation)
+    // and (d+8) 2^-24 of the magnitudes from FP32 accumulation).  Every center
+    // of the stage is a starting center, an average of rows or (re-seeding) a
+    // row, so ||c|| <= max(cm, sqrt(xm)) bounds them all.
     {
       const float sx = sqrtf(xm);
-      st->B = xm + 0.04f * sx * cm + (float)(d_ + 16) * 0x1p-22f * (xm + cm * cm + 2.f * sx * cm);
+      const float cb = fmaxf(cm, sx * (1.0f + 0x1p-20f));
+      st->B = xm + 0.04f * sx * cb + (float)(d_ + 16) * 0x1p-22f * (xm + cb * cb + 2.f * sx * cb);
     }
     st->qcount = 0u;
     st->cmax = cm;
@@ -578,13 +584,16 @@ __global__ __launch_bounds__(256) void k_stage_begin(PassState* __restrict__ st,
     st->uncertain = 0;
     st->pairs = 0;
     st->rows = rows;
+    st->reseed = reseed;
+    st->reseed_j = -1;
   }
 }
 
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
-                       const double* cnorm, int32_t k, int32_t d, int64_t pg, hipStream_t s) {
+                       const double* cnorm, int32_t k, int32_t d, int64_t pg, hipStream_t s,
+                       int reseed) {
   hipLaunchKernelGGL(k_stage_begin, dim3(1), dim3(256), 0, s, st, max_iter, tol, rows, cnorm, k,
-                     d, pg);
+                     d, pg, reseed);
   return hipGetLastError();
 }
 
@@ -1774,6 +1783,33 @@ __device__ __forceinline__ int rerank_vec(const T* __restrict__ xr, int d,
   return bj;
 }
 
+// Dims [t0, t0 + 8) of a row widened to FP64 (zero beyond d).  vec: the row
+// start is 16-byte aligned and d is a multiple of 8, so whole 16-byte loads
+// cover the eight dims.
+template <typename T>
+__device__ __forceinline__ void load8_f64(const T* __restrict__ row, int t0, int d, bool vec,
+                                          double (&v)[8]) {
+  if (vec && t0 + 8 <= d) {
+    if constexpr (sizeof(T) == 2) {
+      const uint4 w = *reinterpret_cast<const uint4*>(row + t0);
+      const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[2 * u] = (double)bf16_lo(w4[u]);
+        v[2 * u + 1] = (double)bf16_hi(w4[u]);
+      }
+    } else {
+      const float4 a = *reinterpret_cast<const float4*>(row + t0);
+      const float4 b = *reinterpret_cast<const float4*>(row + t0 + 4);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+      v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = t0 + e < d ? (double)widen<T>(row[t0 + e]) : 0.0;
+  }
+}
+
 // A copy of v the compiler must keep in a VGPR: with the key mask in an SGPR,
 // a key is then one v_and_or_b32 (one scalar operand per VALU instruction).
 __device__ __forceinline__ int opaque_vgpr(int v) {
@@ -2375,12 +2411,12 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
 // most three tracked keys lie in the band and no slot pair holds two of them; and
 // queued for the re-screen otherwise.
 template <typename T, int KS, int PT, int NW>
-__global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
+__global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) void k_screen_bf16(
     const T* __restrict__ X, int64_t n, int d, int k, const uint16_t* __restrict__ cb16,
     const float* __restrict__ cnB, const float* __restrict__ cw, const double* __restrict__ c64,
     PassState* __restrict__ st, const int32_t* __restrict__ gate, int32_t* __restrict__ labels,
-    int32_t* __restrict__ queue, float* __restrict__ qthr, double* __restrict__ Jpart,
-    long long* __restrict__ upart) {
+    uint32_t* __restrict__ queue, float* __restrict__ qthr, int4* __restrict__ rq_c,
+    double* __restrict__ Jpart, long long* __restrict__ upart) {
   if (gated(gate)) return;
   constexpr int KD = KS * 16;
   constexpr int C8 = KD / 8;                  // 16-byte chunks per center row
@@ -2390,7 +2426,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
   // that reads of one need not wait for the LDS-direct loads into the other
   __shared__ __align__(16) uint16_t cb0[SC * KD], cb1[SC * KD];
   __shared__ __align__(16) float bb0[SC], bb1[SC];
-  __shared__ int cand_j[64 * NW * 4];
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31;
   // wave-uniform (scalar) wave index: the stage-copy loops below then run on
   // the scalar unit
@@ -2641,19 +2676,22 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
       auto apart = [&](float a, float b) {
         return (b - a) > E2 + delta * (fabsf(a) + fabsf(b));
       };
-      const int* cand = nullptr;
+      // a point is decided (best key apart from the rest), re-ranked (its
+      // candidates: the tracked keys within the band of the best, at most four)
+      // or queued for the re-screen (the band may hold untracked centers)
       int nc = 0, label = 0;
+      bool inb[4] = {true, false, false, false};
       bool full = false, decided = false;
       if (k == 1 || (jj[0] < k && apart(v[0], v[1]))) {
         decided = true;
         label = jj[0] < k ? jj[0] : 0;
       } else if (jj[0] < k && (k <= 4 || (apart(v[0], v[3]) && apart(v[0], vm2)))) {
-        int* mine = &cand_j[threadIdx.x * 4];
-        mine[nc++] = jj[0];
+        nc = 1;
 #pragma unroll
-        for (int u = 1; u < 4; ++u)
-          if (jj[u] < k && !apart(v[0], v[u])) mine[nc++] = jj[u];
-        cand = mine;
+        for (int u = 1; u < 4; ++u) {
+          inb[u] = jj[u] < k && !apart(v[0], v[u]);
+          nc += inb[u] ? 1 : 0;
+        }
       } else {
         full = true;
       }
@@ -2665,7 +2703,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
         base_q = __shfl(base_q, 0);
         if (q) {
           const unsigned pos = base_q + __popcll(bq & ((1ull << lane) - 1ull));
-          queue[pos] = (int32_t)ip[p];
+          queue[pos] = (uint32_t)ip[p];  // n < 2^32 on this path
           qthr[pos] = v[0] + E2 + 4.f * delta * (fabsf(v[0]) + E2) + 1e-30f;
         }
       }
@@ -2674,22 +2712,101 @@ __global__ __launch_bounds__(64 * NW, 2) void k_screen_bf16(
         decided = true;
         nc = 0;
       }
-      // the most candidates of a lane in the wave (at most 4)
-      const int ncmax = __ballot(nc >= 4) ? 4 : __ballot(nc >= 3) ? 3 : __ballot(nc >= 2) ? 2
-                      : __ballot(nc >= 1) ? 1 : 0;
       const bool rr = !decided && !full && nc > 0;
-      if (ncmax > 0) {
-        const int lab =
-            ((d & 7) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0)
-                ? rerank_vec<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax,
-                                    ncand)
-                : rerank<T, KS>(X + ip[p] * d, d, h, rr, cand, nc, ncmax, cw, c64, cmax, ncand);
-        if (rr) label = lab;
-      }
-      if (valid[p] && h == 0 && !full) labels[ip[p]] = label < k ? label : 0;
+      // a point to re-rank gets the label -1 and its candidates (k_rerank_list
+      // decides among them in FP64 and writes the label)
+      if (rr && h == 0)
+        rq_c[ip[p]] = make_int4(jj[0], inb[1] ? jj[1] : -1, inb[2] ? jj[2] : -1,
+                                inb[3] ? jj[3] : -1);
+      ncand += __popcll(__ballot(rr && h == 0));
+      // every valid point gets a label here: the re-rank list reads -1 as its
+      // marker, so no point may keep a stale label, and the points queued for
+      // the re-screen hold 0 until the re-screen writes theirs
+      if (valid[p] && h == 0) labels[ip[p]] = rr ? -1 : (full ? 0 : (label < k ? label : 0));
     }
   }
   block_sum_J(0.0, nfull, ncand, Jpart, upart);
+}
+
+// The FP64 re-rank of the points the screen marked (label -1): for each, the
+// nearest of its (at most four) candidates by the direct form sum (x - c)^2 in
+// FP64, lowest index among equal distances.  A wave reads 64 labels at a time;
+// groups of 16 lanes take the marked points four at a time (eight dims per
+// lane, the row and every candidate row requested before any is summed).
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void k_rerank_list(
+    const T* __restrict__ X, int64_t n, int d, int k, const double* __restrict__ c64,
+    const int32_t* __restrict__ gate, int32_t* __restrict__ labels,
+    const int4* __restrict__ rq_c) {
+  if (gated(gate)) return;
+  constexpr int NS8 = (KS * 16 + 127) / 128;  // 128-dim chunks of a row
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const bool vec = (d & 7) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t w0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; w0 < n; w0 += nw * 64) {
+    const int64_t i = w0 + lane;
+    unsigned long long m = __ballot(i < n && labels[i] < 0);
+    while (m) {
+      // the next four marked points of these 64: group g takes the g-th
+      int64_t pt = -1;
+      unsigned long long mm = m;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (mm) {
+          const int b = __ffsll((long long)mm) - 1;
+          mm &= mm - 1ull;
+          if (q == g) pt = w0 + b;
+        }
+      }
+      m = mm;
+      const bool act = pt >= 0;
+      const int4 cj = act ? rq_c[pt] : make_int4(-1, -1, -1, -1);
+      // (defensively, an index outside [0, k) is no candidate)
+      auto ok = [&](int j) { return (j >= 0 && j < k) ? j : -1; };
+      const int cand[4] = {ok(cj.x), ok(cj.y), ok(cj.z), ok(cj.w)};
+      const T* xr = X + (act ? pt : 0) * d;
+      double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s8 = 0; s8 < NS8; ++s8) {
+        const int t0 = 128 * s8 + 8 * li;
+        if (act && t0 < d) {
+          double xv[8];
+          load8_f64<T>(xr, t0, d, vec, xv);
+          double cv[4][8];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double* cr = c64 + (int64_t)(cand[u] >= 0 ? cand[u] : 0) * d + t0;
+#pragma unroll
+            for (int e8 = 0; e8 < 8; ++e8) cv[u][e8] = (cand[u] >= 0 && t0 + e8 < d) ? cr[e8] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int e8 = 0; e8 < 8; ++e8)
+              if (t0 + e8 < d) {
+                const double diff = xv[e8] - cv[u][e8];
+                part[u] = __builtin_fma(diff, diff, part[u]);
+              }
+        }
+      }
+      double bD = INFINITY;
+      int bj = INT_MAX;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double v = part[u];  // the 16 lanes' parts (every lane takes part)
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 1);
+        const int j = cand[u];
+        if (j >= 0 && (v < bD || (v == bD && j < bj))) {
+          bD = v;
+          bj = j;
+        }
+      }
+      if (act && li == 0) labels[pt] = bj < k ? bj : 0;
+    }
+  }
 }
 
 // The re-screen of the points the screen queued: every center whose screened
@@ -2702,7 +2819,7 @@ __global__ __launch_bounds__(512) void k_rescreen_bf16(
     const T* __restrict__ X, int d, int k, const uint16_t* __restrict__ cb16,
     const float* __restrict__ cnB, const float* __restrict__ cw, const double* __restrict__ c64,
     PassState* __restrict__ st, const int32_t* __restrict__ gate, int32_t* __restrict__ labels,
-    const int32_t* __restrict__ queue, const float* __restrict__ qthr,
+    const uint32_t* __restrict__ queue, const float* __restrict__ qthr,
     double* __restrict__ Jpart, long long* __restrict__ upart) {
   if (gated(gate)) return;
   constexpr int KD = KS * 16;
@@ -2746,7 +2863,7 @@ __global__ __launch_bounds__(512) void k_rescreen_bf16(
       }
       if (threadIdx.x < 32) {
         const int j = ct * 32 + threadIdx.x;
-        cbias[threadIdx.x] = j < k ? cnB[j] : 1e30f;
+        cbias[threadIdx.x] = j < k ? cnB[j] : INFINITY;
       }
       __syncthreads();
       v16f acc[PT];
@@ -2767,11 +2884,11 @@ __global__ __launch_bounds__(512) void k_rescreen_bf16(
       for (int p = 0; p < PT; ++p)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          if (valid[p] && acc[p][r] <= thr[p]) {
-            const int j = ct * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          const int j = ct * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (valid[p] && j < k && acc[p][r] <= thr[p]) {
             const int slot = (wave * PT + p) * 32 + pc;
             const int q = atomicAdd(&cand_n[slot], 1);
-            if (q < CMAX && j < k) cand_j[slot * CMAX + q] = j;
+            if (q < CMAX) cand_j[slot * CMAX + q] = j;
           }
         }
     }
@@ -2836,9 +2953,11 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
                                bool mark_labelled = false) {
   __shared__ double wJ[4], wS[4], wN[4];
   __shared__ long long wU[4], wE[4], wP[4];
+  __shared__ int wM[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double J = 0.0, sh = 0.0, nm = 0.0;
   long long U = 0, E = 0, Pc = 0;
+  int jm = INT_MAX;  // lowest empty cluster
   for (int64_t b = tid; b < nb; b += 256) {
     if (!jslots) J += ld_agent(&Jpart[b]);
     U += ld_agent(&upart[2 * b]);
@@ -2848,13 +2967,16 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
     for (int j = tid; j < k; j += 256) {
       sh = fmax(sh, ld_agent(&shiftj[j]));
       nm = fmax(nm, ld_agent(&cnorm[j]));
-      E += ld_agent(&emptyj[j]);
+      const int ej = ld_agent(&emptyj[j]);
+      E += ej;
+      if (ej) jm = min(jm, j);
     }
+  for (int o = 32; o > 0; o >>= 1) jm = min(jm, __shfl_xor(jm, o));
   // fixed-order reductions: lanes of a wave, then the four waves
   J = wave_sum(J); U = wave_sum(U); Pc = wave_sum(Pc); E = wave_sum(E);
   sh = wave_max(sh); nm = wave_max(nm);
   if (lane == 0) {
-    wJ[wv] = J; wU[wv] = U; wP[wv] = Pc; wE[wv] = E; wS[wv] = sh; wN[wv] = nm;
+    wJ[wv] = J; wU[wv] = U; wP[wv] = Pc; wE[wv] = E; wS[wv] = sh; wN[wv] = nm; wM[wv] = jm;
   }
   __syncthreads();
   if (tid == 0) {
@@ -2891,6 +3013,9 @@ __device__ void conclude_block(PassState* __restrict__ st, const double* __restr
       st->iter = it + 1;
       st->converged = St < st->tol ? 1 : 0;
       st->done = (st->converged || it + 1 >= st->max_iter) ? 1 : 0;
+      // re-seeding: the lowest empty cluster moves to the farthest point
+      // (k_farthest, k_reseed), which then redo the stop test
+      if (st->reseed && Et > 0) st->reseed_j = min(min(wM[0], wM[1]), min(wM[2], wM[3]));
     } else if (mark_labelled) {
       st->done = 2;  // a batched labelling pass ran; later launches skip it
     }
@@ -2910,9 +3035,15 @@ __device__ void finalize_center(
     uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
     double* __restrict__ J_hist, double* __restrict__ shift_hist, bool mark_labelled = false,
-    bool biased = false) {
+    bool biased = false, double* __restrict__ trace_c = nullptr,
+    long long* __restrict__ trace_n = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t C = (int64_t)k * (d + 1);
+  // this pass's index in the stage (the last block of the pass advances it
+  // only after every block has read it)
+  const int64_t it = st->iter;
+  if (!update) trace_c = nullptr, trace_n = nullptr;
+  double* tc = trace_c ? trace_c + (it * k + j) * d : nullptr;
   long long* col = slots + (int64_t)j * (d + 1);
   __shared__ long long scnt[kSlots];  // points per slot row (biased sums)
   __shared__ long long sN;
@@ -2949,6 +3080,7 @@ __device__ void finalize_center(
       const double sum = ldexp((double)sv, -F);
       if (update) {
         const double cold = c64[(int64_t)j * d + t];
+        if (tc) tc[t] = cold;
         const double cnew = Nj > 0 ? sum / (double)Nj : cold;
         const double diff = cnew - cold;
         sh += diff * diff;
@@ -2988,6 +3120,7 @@ __device__ void finalize_center(
     }
     if (new_copy) dcn_max(st, re0);
     if (N_out) N_out[j] = (int64_t)Nj;
+    if (trace_n) trace_n[it * k + j] = Nj;
     __threadfence();
     last = atomicAdd(&st->ticket, 1u) == (unsigned)(k - 1) ? 1 : 0;
   }
@@ -3012,11 +3145,171 @@ __global__ __launch_bounds__(256) void k_finalize(
     double* __restrict__ S_out, int64_t* __restrict__ N_out,
     uint16_t* __restrict__ cb16, float* __restrict__ cnB, int kd16,
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
-    double* __restrict__ J_hist, double* __restrict__ shift_hist, int biased) {
+    double* __restrict__ J_hist, double* __restrict__ shift_hist, int biased,
+    double* __restrict__ trace_c, long long* __restrict__ trace_n) {
   if (gated(gate)) return;
   finalize_center(blockIdx.x, slots, jslots, k, d, st, update, c64, cw, cn, cnorm, shiftj, emptyj,
                   S_out, N_out, cb16, cnB, kd16, Jpart, upart, nb, J_hist, shift_hist, false,
-                  biased != 0);
+                  biased != 0, trace_c, trace_n);
+}
+
+// ----------------------------------------------------------------------------
+// Empty-cluster re-seeding (opt-in).  After the update of a pass that left
+// clusters empty, the lowest-index empty cluster takes as its new center the
+// point farthest from its nearest updated center (FP64 direct form; the lowest
+// point index on equal distances).  Its movement joins the pass's largest
+// movement, so the stop test is taken again.  One cluster per pass.
+// ----------------------------------------------------------------------------
+// (D, i) with D larger, or equal D and a lower index, wins.
+__device__ __forceinline__ bool far_better(double D, long long i, double oD, long long oi) {
+  return D > oD || (D == oD && i < oi);
+}
+
+// Per block: the farthest of its points from their nearest center.
+template <typename T>
+__global__ __launch_bounds__(256) void k_farthest(const T* __restrict__ X, int64_t n, int d,
+                                                  int k, const double* __restrict__ c64,
+                                                  const PassState* __restrict__ st,
+                                                  double* __restrict__ fpart,
+                                                  long long* __restrict__ fidx) {
+  if (st->reseed_j < 0) return;
+  __shared__ double wD[4];
+  __shared__ long long wI[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double bD = -1.0;
+  long long bI = LLONG_MAX;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+    const T* xr = X + i * d;
+    double m = INFINITY;
+    for (int j = 0; j < k; ++j) {
+      const double* cj = c64 + (int64_t)j * d;
+      double D = 0.0;
+      for (int t = 0; t < d; ++t) {
+        const double diff = (double)widen<T>(xr[t]) - cj[t];
+        D += diff * diff;  // built without contraction: the product is rounded, then added
+      }
+      m = fmin(m, D);
+    }
+    if (far_better(m, i, bD, bI)) {
+      bD = m;
+      bI = i;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double oD = __shfl_xor(bD, o);
+    const long long oI = __shfl_xor(bI, o);
+    if (far_better(oD, oI, bD, bI)) {
+      bD = oD;
+      bI = oI;
+    }
+  }
+  if (lane == 0) {
+    wD[wv] = bD;
+    wI[wv] = bI;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (far_better(wD[w], wI[w], bD, bI)) {
+        bD = wD[w];
+        bI = wI[w];
+      }
+    fpart[blockIdx.x] = bD;
+    fidx[blockIdx.x] = bI;
+  }
+}
+
+// One block: the farthest point over the partials becomes the center of the
+// empty cluster; its working copies, the bounds of the screens, the largest
+// movement and the stop test follow.
+template <typename T>
+__global__ __launch_bounds__(256) void k_reseed(const T* __restrict__ X, int d, int k,
+                                                double* __restrict__ c64, float* __restrict__ cw,
+                                                float* __restrict__ cn,
+                                                double* __restrict__ cnorm,
+                                                uint16_t* __restrict__ cb16,
+                                                float* __restrict__ cnB, int kd16,
+                                                PassState* __restrict__ st,
+                                                const double* __restrict__ fpart,
+                                                const long long* __restrict__ fidx, int nb,
+                                                double* __restrict__ shift_hist) {
+  const int j = st->reseed_j;
+  if (j < 0) return;
+  __shared__ double wD[4], red[3][4];
+  __shared__ long long wI[4];
+  __shared__ long long far_i;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double bD = -1.0;
+  long long bI = LLONG_MAX;
+  for (int b = tid; b < nb; b += 256)
+    if (far_better(fpart[b], fidx[b], bD, bI)) {
+      bD = fpart[b];
+      bI = fidx[b];
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double oD = __shfl_xor(bD, o);
+    const long long oI = __shfl_xor(bI, o);
+    if (far_better(oD, oI, bD, bI)) {
+      bD = oD;
+      bI = oI;
+    }
+  }
+  if (lane == 0) {
+    wD[wv] = bD;
+    wI[wv] = bI;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w)
+      if (far_better(wD[w], wI[w], bD, bI)) {
+        bD = wD[w];
+        bI = wI[w];
+      }
+    far_i = bI;
+  }
+  __syncthreads();
+  const T* xr = X + far_i * d;
+  double mv = 0.0, nn = 0.0, ee = 0.0;
+  for (int t = tid; t < d; t += 256) {
+    const double x = (double)widen<T>(xr[t]);
+    const double diff = x - c64[(int64_t)j * d + t];
+    mv += diff * diff;
+    nn += x * x;
+    c64[(int64_t)j * d + t] = x;
+    cw[(int64_t)j * d + t] = (float)x;
+    if (cb16) {
+      const uint16_t b = f32_to_bf16((float)(-2.0 * x));
+      cb16[cb16_at(j, t, kd16)] = b;
+      const double e = bf16_err(b, x);
+      ee += e * e;
+    }
+  }
+  mv = wave_sum(mv);
+  nn = wave_sum(nn);
+  ee = wave_sum(ee);
+  if (lane == 0) {
+    red[0][wv] = mv;
+    red[1][wv] = nn;
+    red[2][wv] = ee;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double m2 = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    const double n2 = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    const double e2 = (red[2][0] + red[2][1]) + (red[2][2] + red[2][3]);
+    cn[j] = (float)n2;
+    cnorm[j] = sqrt(n2);
+    if (cnB) cnB[j] = (float)(n2 + (double)st->B);
+    if (cb16)
+      st->dcn = fmaxf(st->dcn, (float)(sqrt(e2) * (1.0 + 0x1p-40)) * (1.0f + 0x1p-22f));
+    st->cmax = fmaxf(st->cmax, (float)(sqrt(n2) * (1.0 + 0x1p-20)) * (1.0f + 0x1p-20f));
+    const double sh = fmax(st->shift, sqrt(m2));
+    st->shift = sh;
+    if (shift_hist) shift_hist[st->iter - 1] = sh;
+    st->converged = sh < st->tol ? 1 : 0;
+    st->done = (st->converged || st->iter >= st->max_iter) ? 1 : 0;
+    st->reseed_j = -1;
+  }
 }
 
 // J and FP64-check counts of a labelling pass of the fused paths.  One block.
@@ -3168,7 +3461,7 @@ __global__ __launch_bounds__(64) void k_prep_bf16(const double* __restrict__ c64
     e2 += __shfl_xor(e2, o);
   }
   if (lane == 0) {
-    cnB[j] = j < k ? (float)(acc + (double)st->B) : 1e30f;
+    cnB[j] = j < k ? (float)(acc + (double)st->B) : INFINITY;
     dcn_max(st, e2);
     __threadfence();
     if (atomicAdd(&st->ticket, 1u) == gridDim.x - 1) {
@@ -3311,12 +3604,13 @@ static void visit_screen(int ks, F&& f) {
     case 1: f(k_screen_bf16<T, 1, 2, 4>); break;
     case 2: f(k_screen_bf16<T, 2, 2, 4>); break;
     case 4: f(k_screen_bf16<T, 4, 1, 8>); break;
-    case 8: f(k_screen_bf16<T, 8, 2, 4>); break;
+    case 8: f(k_screen_bf16<T, 8, 2, 8>); break;
     default: f(k_screen_bf16<T, 16, 1, 8>); break;
   }
 }
-constexpr int screen_threads(int ks) { return (ks == 4 || ks >= 16) ? 512 : 256; }
-constexpr int kScreenPoints = 256;  // points per block and tile (NW * PT * 32)
+// threads (64 NW) and points (NW PT 32) per block of the screen for each K-step count
+constexpr int screen_threads(int ks) { return (ks == 4 || ks >= 8) ? 512 : 256; }
+constexpr int screen_points(int ks) { return ks == 8 ? 512 : 256; }
 
 template <typename T, typename F>
 static void visit_rescreen(int ks, F&& f) {
@@ -3357,7 +3651,8 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   const bool screen = precision == 2 || (precision == 0 && dtype == 1 && d >= 32);
   const bool small = d <= 16 && k <= 128 &&
                      kk * (size_t)(std::max(p.dmax, 2) + 2) * 8 + kk * (dd + 1) * 8 <= budget;
-  p.bf16 = d <= 256 && screen && !small;
+  // (the screen packs center indices into 27 bits)
+  p.bf16 = d <= 256 && screen && !small && k < (1 << 27);
   if (p.bf16) {
     p.ks = d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 4 : d <= 128 ? 8 : 16;
     p.dmax = 0;
@@ -3369,7 +3664,7 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   const size_t lds_fused = ((kk * (size_t)p.dmax + kk) * 4 + 15) / 16 * 16 + kk * (dd + 1) * 8;
   int64_t work = 1;  // independent units of the assignment kernel (waves' tiles)
   if (p.bf16) {
-    work = (rows + kScreenPoints - 1) / kScreenPoints;
+    work = (rows + screen_points(p.ks) - 1) / screen_points(p.ks);
   } else if (small && (screen || precision == 0)) {
     // small d: the fused pass scores on the BF16 matrix cores (certified).
     // Asked for the BF16 screen: one BF16 product per dim, whose band
@@ -3522,9 +3817,23 @@ static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* g
     hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(screen_threads(p.ks)), 0, s,
                        (const T*)b.X, b.n, b.d,
                        b.k, (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
-                       (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr, b.Jpart,
-                       b.upart);
+                       (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr, b.rq_c,
+                       b.Jpart, b.upart);
   });
+}
+
+// The screen's re-rank list, in FP64.
+template <typename T>
+static void dispatch_rerank(const PassBufs& b, const PassPlan& p, const int32_t* gate,
+                            hipStream_t s) {
+  // a wave per 64 points, up to 4096 blocks (16 waves per SIMD on 256 CUs)
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 255) / 256, 4096));
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, (const T*)b.X, b.n, b.d, b.k,
+                       (const double*)b.c64, gate, b.labels, (const int4*)b.rq_c);
+  };
+  if (p.ks <= 8) go(k_rerank_list<T, 8>);
+  else go(k_rerank_list<T, 16>);
 }
 
 // The points with more than four candidates, re-screened (the second half of
@@ -3535,7 +3844,7 @@ static void dispatch_rescreen(const PassBufs& b, const PassPlan& p, const int32_
   visit_rescreen<T>(p.ks, [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(512), 0, s, (const T*)b.X, b.d, b.k,
                        (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
-                       (const double*)b.c64, b.st, gate, b.labels, (const int32_t*)b.queue,
+                       (const double*)b.c64, b.st, gate, b.labels, (const uint32_t*)b.queue,
                        (const float*)b.qthr, b.Jpart + p.blocks, b.upart + 2 * p.blocks);
   });
 }
@@ -3560,8 +3869,13 @@ hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStrea
   const int32_t* gate = update ? &b.st->done : nullptr;
   const int64_t nb = p.bf16 ? 2 * p.blocks : p.blocks;
   if (p.bf16) {
-    if (b.dtype == 0) dispatch_rescreen<float>(b, p, gate, s);
-    else dispatch_rescreen<uint16_t>(b, p, gate, s);
+    if (b.dtype == 0) {
+      dispatch_rerank<float>(b, p, gate, s);
+      dispatch_rescreen<float>(b, p, gate, s);
+    } else {
+      dispatch_rerank<uint16_t>(b, p, gate, s);
+      dispatch_rescreen<uint16_t>(b, p, gate, s);
+    }
   }
   // The sorted update makes the sums of an update pass and, with the BF16
   // screen, J of every pass; the FP32 kernels add J themselves in a labelling
@@ -3574,7 +3888,23 @@ hipError_t pass_rest(const PassBufs& b, const PassPlan& p, bool update, hipStrea
                        b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, b.S_out, b.N_out,
                        copy16(p) ? b.cb16 : nullptr, copy16(p) ? b.cnB : nullptr, p.ks * 16,
                        (const double*)b.Jpart, (const long long*)b.upart, nb, b.J_hist,
-                       b.shift_hist, (p.fscreen && p.fsplit) ? 1 : 0);
+                       b.shift_hist, (p.fscreen && p.fsplit) ? 1 : 0, b.trace_c, b.trace_n);
+    if (update && b.fpart) {
+      // re-seeding: both kernels return at once unless this pass left a cluster empty
+      const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 255) / 256,
+                                                                            kFarBlocks));
+      auto far = [&](auto* x) {
+        using T = std::remove_const_t<std::remove_pointer_t<decltype(x)>>;
+        hipLaunchKernelGGL(k_farthest<T>, dim3(g), dim3(256), 0, s, x, b.n, b.d, b.k,
+                           (const double*)b.c64, (const PassState*)b.st, b.fpart, b.fidx);
+        hipLaunchKernelGGL(k_reseed<T>, dim3(1), dim3(256), 0, s, x, b.d, b.k, b.c64, b.cw, b.cn,
+                           b.cnorm, copy16(p) ? b.cb16 : nullptr, copy16(p) ? b.cnB : nullptr,
+                           p.ks * 16, b.st, (const double*)b.fpart, (const long long*)b.fidx,
+                           (int)g, b.shift_hist);
+      };
+      if (b.dtype == 0) far((const float*)b.X);
+      else far((const uint16_t*)b.X);
+    }
   } else {
     hipLaunchKernelGGL(k_sum_J, dim3(1), dim3(256), 0, s, b.st, (const double*)b.Jpart,
                        (const long long*)b.upart, nb);

@@ -69,6 +69,10 @@ struct PassState {
   // the maximum over the blocks of the kernel that writes the copy.
   float dcn;
   uint32_t dcn_bits;
+  // Empty-cluster re-seeding (opt-in): reseed = 1 turns it on for the stage;
+  // reseed_j is the empty cluster the current pass re-seeds (-1: none).
+  int32_t reseed;
+  int32_t reseed_j;
 };
 
 // One instance of a batched pass: many independent k-means problems advance
@@ -125,7 +129,8 @@ hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, PassStat
 hipError_t prep_centers(const double* c64, int32_t k, int32_t d, float* cw, float* cn,
                         double* cnorm, hipStream_t s);
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
-                       const double* cnorm, int32_t k, int32_t d, int64_t pg, hipStream_t s);
+                       const double* cnorm, int32_t k, int32_t d, int64_t pg, hipStream_t s,
+                       int reseed = 0);
 
 struct PassBufs {
   const void* X; int dtype; int64_t n; int32_t d; int32_t k;
@@ -138,15 +143,23 @@ struct PassBufs {
   long long* stot;     // [scan tiles + 1] tile totals of the offset scan
   long long* rstart;   // [k + 1] first position of every label's run
   uint16_t* cb16;      // bf16_rows(k) x ks*16 BF16 (-2 c) of the BF16 screen, tiled (cb16_at)
-  float* cnB;          // [bf16_rows(k)] ||c||^2 + B of the BF16 screen (1e30 on padding rows)
-  int32_t* queue;      // [n] points of the BF16 screen with more than 4 candidates
+  float* cnB;          // [bf16_rows(k)] ||c||^2 + B of the BF16 screen (+inf on padding rows)
+  uint32_t* queue;     // [n] points of the BF16 screen with more than 4 candidates (n < 2^32)
+  int4* rq_c;          // [n] candidates of the points the BF16 screen marks for the FP64
+                       //   re-rank (label -1): up to four center indices, -1 = none
   float* qthr;         // [n] their score thresholds
   double* Jpart; long long* upart;
   int32_t* labels;     // labels of the rows (required by the split path)
   PassState* st;
   double* J_hist; double* shift_hist;
   double* S_out; int64_t* N_out;   // optional exact sums / counts of the pass
+  // optional per-pass trace, indexed by the stage's pass: the centers a pass
+  // starts from ([pass][k][d]) and its cluster sizes ([pass][k])
+  double* trace_c; long long* trace_n;
+  // re-seeding: per-block farthest-point partials of k_farthest (kFarBlocks)
+  double* fpart; long long* fidx;
 };
+constexpr int kFarBlocks = 1024;       // grid of the farthest-point search
 
 // Geometry chosen once per (rows, d, k): fused or split path and block counts.
 struct PassPlan {

@@ -195,7 +195,12 @@ struct Job {
   long long* upart = nullptr;
   double t_submit = 0, t_admit = 0, t_done = 0;
   int64_t unc2 = 0;  // FP64 checks counted by the slow stage's passes
+  int64_t passed_over = 0;  // admission rounds in which later problems went ahead
 };
+
+// Admission rounds a waiting problem may be passed by later, smaller ones;
+// beyond this the queue holds behind it until it fits (no starvation).
+constexpr int64_t kMaxPassOver = 64;
 
 int elt_size(km_dtype t) { return t == KM_F32 ? 4 : 2; }
 
@@ -580,6 +585,10 @@ struct km_server {
   size_t in_use = 0, budget = 0;
   km_server_counters ctr{};
   std::thread th;
+  // threads inside km_server_wait; km_server_destroy frees the server only
+  // after the last one has left
+  int waiters = 0;
+  std::condition_variable cv_left;
 
   void loop();
 };
@@ -594,7 +603,9 @@ void km_server::loop() {
       cv_work.wait(lk, [&] { return stop || !pending.empty() || !active.empty(); });
       if (stop) break;
       // admission by footprint, in arrival order; a problem that does not fit
-      // yet lets smaller later ones pass
+      // yet lets smaller later ones pass, until it has been passed over
+      // kMaxPassOver times: then nothing behind it is admitted before it
+      Job* blocked = nullptr;
       for (auto it = pending.begin(); it != pending.end() &&
                                       (int)(active.size() + admitted_now.size()) < cfg.max_active;) {
         if (in_use + (*it)->bytes <= budget) {
@@ -603,9 +614,12 @@ void km_server::loop() {
           admitted_now.push_back(std::move(*it));
           it = pending.erase(it);
         } else {
+          if (!blocked) blocked = it->get();
+          if ((*it)->passed_over >= kMaxPassOver) break;
           ++it;
         }
       }
+      if (blocked && !admitted_now.empty()) ++blocked->passed_over;
       ctr.pending = (int64_t)pending.size();
     }
     std::vector<std::unique_ptr<Job>> failed_now;
@@ -654,7 +668,7 @@ void km_server::loop() {
         finished[jp->ticket] = std::move(jp);
       }
       ctr.admitted += (int64_t)admitted_now.size();
-      ctr.active = (int64_t)active.size();
+      ctr.active = (int64_t)active.size();  // written here, under mu, read by km_server_stats
       ctr.peak_active = std::max(ctr.peak_active, ctr.active);
       ctr.bytes_in_use = in_use;
       ctr.peak_bytes = std::max(ctr.peak_bytes, in_use);
@@ -840,6 +854,15 @@ km_status km_server_wait(km_server* srv, uint64_t ticket, km_result* out, int64_
   std::unique_lock<std::mutex> lk(srv->mu);
   if (!srv->where.count(ticket)) return fail(KM_ENOTFOUND, "unknown ticket %llu",
                                              (unsigned long long)ticket);
+  // registered as a waiter until return, so that km_server_destroy does not
+  // free the server under this thread
+  ++srv->waiters;
+  struct Leave {
+    km_server* s;
+    ~Leave() {
+      if (--s->waiters == 0) s->cv_left.notify_all();
+    }
+  } leave{srv};
   auto ready = [&] { return srv->finished.count(ticket) > 0; };
   if (timeout_us < 0) {
     srv->cv_done.wait(lk, ready);
@@ -859,9 +882,8 @@ km_status km_server_stats(km_server* srv, km_server_counters* out) {
   g_err.clear();
   if (!srv || !out) return fail(KM_EINVAL, "srv and out must not be NULL");
   std::lock_guard<std::mutex> lk(srv->mu);
-  *out = srv->ctr;
+  *out = srv->ctr;  // the scheduler thread owns `active`; ctr.active is its count
   out->pending = (int64_t)srv->pending.size();
-  out->active = (int64_t)srv->active.size();
   return KM_OK;
 }
 
@@ -874,6 +896,12 @@ km_status km_server_destroy(km_server* srv) {
   }
   srv->cv_work.notify_all();
   if (srv->th.joinable()) srv->th.join();
+  // the scheduler has cancelled every unfinished problem (KM_ECANCELLED) and
+  // woken the waiters; they collect their results before the server goes
+  {
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_left.wait(lk, [&] { return srv->waiters == 0; });
+  }
   srv->eng.reset();
   (void)hipStreamDestroy(srv->s);
   delete srv;

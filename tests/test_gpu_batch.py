@@ -155,3 +155,48 @@ def test_server_rejects_bad_request_and_unknown_ticket():
         res = km.km_result()
         rc = km.load().km_server_wait(srv._h, 12345, res, 0)
         assert rc == km.KM_ENOTFOUND
+
+
+def test_server_over_budget_submit_is_enomem():
+    with km.Server(hbm_budget_bytes=1 << 20) as srv:
+        with pytest.raises(km.KMeansError) as e:
+            srv.submit(torch.from_numpy(_problem(200_000, 8, 8, 1, "f32")), 8, 0.1, 0)
+        assert e.value.status == km.KM_ENOMEM
+        assert srv.stats()["submitted"] == 0
+
+
+def test_server_destroy_with_jobs_in_flight_and_blocked_waiter():
+    """Destroy while problems run and wait, with another thread blocked in
+    km_server_wait: destroy returns, the waiter returns KM_ECANCELLED (or its
+    result, had it finished first), and nothing else happens to the process."""
+    import threading
+
+    Xs = [_problem(200_000, 32, 64, 300 + i, "f32") for i in range(6)]
+    # room for two problems at a time: four wait in the queue; thousands of
+    # passes each (tol 0) keep the two admitted ones running
+    srv = km.Server(hbm_budget_bytes=70 << 20)
+    tickets = [srv.submit(torch.from_numpy(X), 64, 0.05, i, (2000, 4000), (0.0, 0.0))
+               for i, X in enumerate(Xs)]
+    outcome = {}
+
+    def waiter():
+        try:
+            srv.wait(tickets[-1])
+            outcome["status"] = km.KM_OK
+        except km.KMeansError as e:
+            outcome["status"] = e.status
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    import time
+    time.sleep(1.0)  # the waiter is inside km_server_wait by now
+    st = srv.stats()
+    assert st["pending"] + st["active"] > 0
+    srv.close()  # km_server_destroy
+    th.join(timeout=60)
+    assert not th.is_alive()
+    assert outcome["status"] in (km.KM_OK, km.KM_ECANCELLED)
+    # the device is still usable
+    Xh = _problem(2_000, 4, 5, 11, "f32")
+    _check_against_oracle(Xh, *km.kmeans_fit_batch([(to_device(Xh), 5, 0.1, 1, 20, 1e-4)])[0],
+                          5, 0.1, 1, (20, 20), (1e-4, 1e-4), "after destroy")

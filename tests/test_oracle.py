@@ -319,3 +319,129 @@ def test_shift_is_euclidean_movement():
     X2 = np.vstack([X, [[105.0, 112.0]]])
     st = oracle.step(X2, np.array([[0.0, 0.0], [100.0, 100.0]]))
     assert st.shift == 13.0
+
+
+# ----------------------------------------------------------------- J_stage1
+def test_J_stage1_is_the_last_fast_pass_before_its_update():
+    """k = 1 with a tolerance so large that the fast stage stops after its
+    first pass: J_stage1 is the sum over the subset of the squared distances to
+    the initial center (the point with the smallest key), not to the subset's
+    mean (the updated center).  Computed here from the sampled indices alone."""
+    rng = np.random.default_rng(12)
+    X = rng.normal(2.0, 3.0, size=(3000, 4))
+    f, seed = 0.05, 17
+    m = oracle.subset_size(len(X), 1, f)
+    sub, ini = oracle.select(len(X), m, 1, seed)
+    Y = X[sub]
+    fit = oracle.fit(X, 1, f, seed, (5, 5), (1e300, 1e-300))
+    assert fit.info["iters"][0] == 1
+    want = ((Y - X[ini[0]]) ** 2).sum()
+    assert fit.info["J_stage1"] == pytest.approx(want, rel=1e-13)
+    assert abs(fit.info["J_stage1"] - ((Y - Y.mean(0)) ** 2).sum()) > 1e-3 * want
+    # more passes: J_stage1 is J of the last pass, i.e. at the subset's mean
+    fit = oracle.fit(X, 1, f, seed, (5, 5), 1e-300)
+    assert fit.info["iters"][0] == 2
+    assert fit.info["J_stage1"] == pytest.approx(((Y - Y.mean(0)) ** 2).sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_J_stage1_equals_hand_replay(seed):
+    X = _mixture(seed + 30)
+    k, f, tol = 5, 0.05, 1e-6
+    n = len(X)
+    sub, ini = oracle.select(n, oracle.subset_size(n, k, f), k, seed)
+    Y = np.ascontiguousarray(X[sub])
+    C = X[ini].astype(np.float64)
+    Jlast = None
+    for _ in range(100):
+        st = oracle.step(Y, C)
+        Jlast, C = st.J, st.C_new
+        if st.shift < tol:
+            break
+    fit = oracle.fit(X, k, f, seed, 100, tol)
+    assert fit.info["J_stage1"] == Jlast
+
+
+# ------------------------------------------------------------ per-pass trace
+def test_trace_hand_computed_table():
+    """A Table 1 style trace worked out by hand: 1-D points 0, 1, 2, 10, 11, 12,
+    two centers started at 0 and 1 (slow stage only).  Pass 1: {0} and
+    {1, 2, 10, 11, 12} -> centers 0 and 7.2.  Pass 2: {0, 1, 2} and {10, 11, 12}
+    -> 1 and 11.  Pass 3: the same clusters, no movement, stop."""
+    X = np.array([[0.0], [1.0], [2.0], [10.0], [11.0], [12.0]])
+    fit = oracle.fit(X, 2, 1.0, 0, (1, 10), (0.0, 1e-9), init_centers=np.array([[0.0], [1.0]]),
+                     skip_stage1=True, trace=True)
+    assert fit.info["iters"][1] == 3
+    assert np.array_equal(fit.trace_centers[1][:, :, 0], [[0, 1], [0, 7.2], [1, 11]])
+    assert np.array_equal(fit.trace_counts[1], [[1, 5], [3, 3], [3, 3]])
+    assert np.array_equal(fit.centers[:, 0], [1, 11])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_trace_rows_chain_the_passes(seed):
+    """Row 0 of the fast stage holds the sampled initial centers; every later row
+    holds the previous pass's new centers; the fast stage's new centers start the
+    slow stage; counts are the sizes of the labels of each pass."""
+    X = _mixture(seed + 40, n=3000)
+    k, f, tol = 6, 0.1, 1e-6
+    fit = oracle.fit(X, k, f, seed, 100, tol, trace=True)
+    n = len(X)
+    sub, ini = oracle.select(n, oracle.subset_size(n, k, f), k, seed)
+    tc, tn = fit.trace_centers, fit.trace_counts
+    assert np.array_equal(tc[0][0], X[ini].astype(np.float64))
+    Ys = (np.ascontiguousarray(X[sub]), X)
+    for s in range(2):
+        for t in range(len(tc[s])):
+            st = oracle.step(Ys[s], tc[s][t])
+            assert np.array_equal(tn[s][t], np.bincount(st.labels, minlength=k))
+            nxt = tc[s][t + 1] if t + 1 < len(tc[s]) else (tc[1][0] if s == 0 else fit.centers)
+            assert np.array_equal(nxt, st.C_new)
+    assert tn[0].sum(1).tolist() == [len(sub)] * len(tn[0])
+    assert tn[1].sum(1).tolist() == [n] * len(tn[1])
+
+
+# --------------------------------------------------- empty-cluster re-seeding
+def test_reseed_moves_empty_center_to_farthest_point():
+    """Two identical centers at 1 over the points 0, 1, 2, 100: the second one
+    gets no point (lowest index on ties).  The update puts the first at the mean
+    25.75; the re-seed sends the second to the point farthest from its nearest
+    updated center, 100 (distance 74.25 to 25.75), a movement of 99."""
+    X = np.array([[0.0], [1.0], [2.0], [100.0]])
+    C = np.array([[1.0], [1.0]])
+    keep = oracle.step(X, C)
+    assert keep.empty == 1 and np.array_equal(keep.C_new[:, 0], [25.75, 1.0])
+    assert keep.shift == 24.75
+    re = oracle.step(X, C, reseed=True)
+    assert re.empty == 1 and np.array_equal(re.N, [4, 0])
+    assert np.array_equal(re.C_new[:, 0], [25.75, 100.0]) and re.shift == 99.0
+    assert np.array_equal(re.labels, keep.labels) and re.J == keep.J
+
+
+def test_reseed_tie_goes_to_lowest_point_and_one_cluster_per_pass():
+    """Points -10, 0, 10 and three centers at 0: clusters 1 and 2 are empty; only
+    cluster 1 is re-seeded, to -10 (as far as 10 from the updated center 0, and
+    first); cluster 2 keeps its center until a later pass."""
+    X = np.array([[-10.0], [0.0], [10.0]])
+    st = oracle.step(X, np.zeros((3, 1)), reseed=True)
+    assert st.empty == 2
+    assert np.array_equal(st.C_new[:, 0], [0.0, -10.0, 0.0]) and st.shift == 10.0
+    st2 = oracle.step(X, st.C_new, reseed=True)
+    # next pass from 0, -10, 0: -10 joins cluster 1; 0 and 10 go to cluster 0
+    # (ties with cluster 2), whose mean is 5; cluster 2 is empty and takes the
+    # point farthest from its nearest of 5, -10, 0: 10 (at 5 from 5)
+    assert np.array_equal(st2.N, [2, 1, 0]) and st2.empty == 1
+    assert np.array_equal(st2.C_new[:, 0], [5.0, -10.0, 10.0])
+
+
+def test_reseed_fit_ends_without_empty_clusters():
+    """Two starting centers far outside the data never win a point under the
+    keep rule; with re-seeding (one per pass) every cluster ends with members
+    and J is lower."""
+    X = _mixture(50, n=2000, d=2, k=4, spread=20.0).astype(np.float64)
+    C0 = np.array([X[0], X[1], [1e6, 1e6], [-1e6, 1e6]])
+    keep = oracle.fit(X, 4, 1.0, 0, (1, 100), 1e-9, init_centers=C0, skip_stage1=True)
+    re = oracle.fit(X, 4, 1.0, 0, (1, 100), 1e-9, init_centers=C0, skip_stage1=True, reseed=True)
+    assert keep.info["empty"][1] == 2
+    assert re.info["empty"][1] == 0 and re.info["converged"][1] == 1
+    assert re.info["J"] < keep.info["J"]
+    _lloyd_stable(X, re.labels, re.centers, 4)
