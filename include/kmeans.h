@@ -140,6 +140,23 @@ km_status kmeans_fit_ex(const void* X, int64_t n, int32_t d, int32_t k, double s
                         uint64_t seed, const km_options* opt, float* centers_out,
                         int32_t* labels_out, km_info* info);
 
+/*
+ * kmeans_fit_ex for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * call's scratch is a fixed device array of KM_STATIC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends, and the call
+ * allocates nothing (no device, pinned or event allocation; profiling with
+ * kmeans_profile_begin does not record it).  opt->workspace must be NULL.
+ * KM_ENOMEM when kmeans_workspace_bytes() for the sizes and options exceeds
+ * KM_STATIC_SCRATCH_BYTES.  Every call on a GPU uses that GPU's one array:
+ * calls that overlap in time on the same GPU (other threads or streams) race
+ * and must not be made.  Results are those of kmeans_fit_ex.
+ */
+#define KM_STATIC_SCRATCH_BYTES (64u << 20)
+km_status kmeans_fit_static(const void* X, int64_t n, int32_t d, int32_t k,
+                            double subset_frac, uint64_t seed, const km_options* opt,
+                            float* centers_out, int32_t* labels_out, km_info* info);
+
 /* Options equivalent to kmeans_fit(max_iter, tol) on FP32 data. */
 void kmeans_default_options(km_options* opt, int32_t max_iter, double tol);
 

@@ -25,7 +25,8 @@ EXPORTS = ("kmeans_fit", "kmeans_fit_ex", "kmeans_default_options", "kmeans_work
            "km_sample", "km_step", "km_assign", "kmeans_last_error", "kmeans_profile_begin",
            "kmeans_profile_end", "kmeans_release_memory", "kmeans_fit_batch", "km_tune_query",
            "km_server_create", "km_server_submit", "km_server_wait", "km_server_stats",
-           "km_server_destroy", "km_probe_stream_read", "km_probe_mfma_bf16")
+           "km_server_destroy", "km_probe_stream_read", "km_probe_mfma_bf16",
+           "kmeans_fit_static")
 
 
 class KMeansError(RuntimeError):
@@ -117,6 +118,8 @@ def load():
     lib.kmeans_fit.argtypes = [vp, i64, i32, i32, f64, u64, i32, f64, vp, vp, P(km_info)]
     lib.kmeans_fit_ex.argtypes = [vp, i64, i32, i32, f64, u64, P(km_options), vp, vp,
                                   P(km_info)]
+    lib.kmeans_fit_static.argtypes = lib.kmeans_fit_ex.argtypes
+    lib.kmeans_fit_static.restype = ctypes.c_int
     lib.kmeans_default_options.argtypes = [P(km_options), i32, f64]
     lib.kmeans_default_options.restype = None
     lib.kmeans_workspace_bytes.argtypes = [i64, i32, i32, f64, P(km_options)]
@@ -283,6 +286,21 @@ def _fit_call(entry, X, k, subset_frac, seed, opt, labels, centers64, history, t
         out["trace_centers"] = (tc[:it[0]].copy(), tc[int(mi[0]):int(mi[0]) + it[1]].copy())
         out["trace_counts"] = (tn[:it[0]].copy(), tn[int(mi[0]):int(mi[0]) + it[1]].copy())
     return C, L, out
+
+
+def kmeans_fit_static(X: torch.Tensor, k: int, subset_frac: float, seed: int, max_iter=50,
+                      tol=1e-4, *, precision: str = "auto", init_centers=None,
+                      skip_stage1: bool = False, labels: bool = True, centers64: bool = False,
+                      history: bool = False, stream=None, check_finite: bool = False,
+                      reseed: bool = False, trace: bool = False):
+    """kmeans_fit_ex with the library's fixed scratch array: no device memory is
+    allocated by the call (C: kmeans_fit_static; the tensors this binding
+    creates for the outputs are the caller's side)."""
+    lib = load()
+    opt, keep = _options(X, k, max_iter, tol, precision, init_centers, skip_stage1, stream,
+                         None, check_finite, reseed)
+    return _fit_call(lib.kmeans_fit_static, X, k, subset_frac, seed, opt, labels, centers64,
+                     history, trace)
 
 
 def kmeans_workspace_bytes(n: int, d: int, k: int, subset_frac: float, max_iter=50,
