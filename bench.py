@@ -135,11 +135,18 @@ def cpu_baseline(w, rows: int):
                        f"passes {f.info['iters']}")}
 
 
-def serve_stream(count: int, rate: float, budget: int) -> dict:
-    """The serving workload: `count` requests with Poisson arrivals at `rate` per
-    second (mixed n, d, k; data generated from each request's seed just before
-    it arrives), submitted to one server; latency = admission wait + run, from
-    the server's own clock."""
+SERVE_POOL = 500  # distinct requests generated before the clock starts
+
+
+def serve_stream(count: int, rate: float, budget: int, pool: int = SERVE_POOL) -> dict:
+    """The serving workload: `count` requests submitted to one server, with
+    Poisson arrivals at `rate` per second (rate 0: all at once, the closed-loop
+    capacity).  The requests follow the serving stream's distribution (mixed n,
+    d, k; data from each request's seed); the first `pool` of them are generated
+    on the host before the clock starts and request i reuses request i % pool's
+    shape and data with its own fit seed, so that the host generator does not
+    bound the arrival rate.  Latency = admission wait + run, from the server's
+    own clock."""
     import threading
     import numpy as np
     import torch
@@ -147,10 +154,19 @@ def serve_stream(count: int, rate: float, budget: int) -> dict:
     import paper_1108_1351_amd as km
     import synth
 
-    reqs = synth.serving_stream(count, rate)
+    reqs = synth.serving_stream(min(count, pool), 1.0)
+    tensors = []
+    for r in reqs:
+        w = r.workload
+        Xh = w.data()
+        X = torch.from_numpy(Xh.view(np.int16) if w.dtype == "bf16" else Xh)
+        tensors.append((X.view(torch.bfloat16) if w.dtype == "bf16" else X, w))
+    print(f"[serve] {len(tensors)} distinct requests generated", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count)) if rate > 0 else \
+        np.zeros(count)
     tickets = [None] * count
     lat, evals, errs = [], 0, 0
-    done = threading.Event()
     with km.Server(hbm_budget_bytes=budget) as srv:
         # warm the autotuner for every (dtype, d, k bucket) the stream can use
         for d in (2, 8, 32, 128):
@@ -159,39 +175,36 @@ def serve_stream(count: int, rate: float, budget: int) -> dict:
         t0 = time.perf_counter()
 
         def produce():
-            for i, r in enumerate(reqs):
-                w = r.workload
-                Xh = w.data()
-                X = torch.from_numpy(Xh.view(np.int16) if w.dtype == "bf16" else Xh)
-                if w.dtype == "bf16":
-                    X = X.view(torch.bfloat16)
+            for i in range(count):
+                X, w = tensors[i % len(tensors)]
                 now = time.perf_counter() - t0
-                if r.arrival_s > now:
-                    time.sleep(r.arrival_s - now)
-                tickets[i] = srv.submit(X, w.k, w.subset_frac, w.fit_seed, w.max_iter, w.tol,
+                if arrivals[i] > now:
+                    time.sleep(arrivals[i] - now)
+                tickets[i] = srv.submit(X, w.k, w.subset_frac, i, w.max_iter, w.tol,
                                         labels=False)
-                if i % 500 == 0:
+                if i % 1000 == 0:
                     print(f"[serve] submitted {i + 1}/{count}", file=sys.stderr, flush=True)
-            done.set()
 
         th = threading.Thread(target=produce)
         th.start()
         for i in range(count):
             while tickets[i] is None:
-                time.sleep(0.0005)
+                time.sleep(0.0002)
             try:
                 _, _, info = srv.wait(tickets[i])
                 lat.append(info["queue_seconds"] + info["run_seconds"])
                 evals += info["dist_evals"]
             except km.KMeansError:
                 errs += 1
-            if i % 500 == 0:
+            if i % 1000 == 0:
                 print(f"[serve] completed {i + 1}/{count}", file=sys.stderr, flush=True)
         th.join()
         t1 = time.perf_counter()
         st = srv.stats()
     lat = np.array(lat)
-    return {"requests": count, "rate_per_s": rate, "failed": errs,
+    return {"requests": count, "distinct": len(tensors), "rate_per_s": rate, "failed": errs,
+            "offered_per_s": count / max(1e-9, float(arrivals[-1])) if rate > 0 else None,
+            "completed_per_s": count / (t1 - t0),
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "mean_s": float(lat.mean()), "wall_s": t1 - t0,
             "evals_per_s": evals / (t1 - t0), "rounds": st["rounds"],
@@ -295,7 +308,10 @@ def main() -> int:
                     help="only run a plain device copy of BYTES bytes (HBM counter scale)")
     ap.add_argument("--serve", type=int, default=0, metavar="REQUESTS",
                     help="run the serving stream of REQUESTS requests instead of the fit bench")
-    ap.add_argument("--serve-rate", type=float, default=100.0, help="arrivals per second")
+    ap.add_argument("--serve-rate", type=float, default=100.0,
+                    help="arrivals per second (0: all at once, the closed-loop capacity)")
+    ap.add_argument("--serve-protocol", action="store_true",
+                    help="closed-loop capacity C, then Poisson arrivals at 0.5 C and 0.9 C")
     ap.add_argument("--serve-budget", type=int, default=0, help="server HBM budget (bytes)")
     ap.add_argument("--speedup", action="store_true",
                     help="run the two-stage vs normal k-means sweep instead of the fit bench")
@@ -311,14 +327,21 @@ def main() -> int:
         if args.gpus != 1:
             print("bench.py measures one GPU", file=sys.stderr)
             return 2
-        r = serve_stream(args.serve, args.serve_rate, args.serve_budget)
-        out = {"metric": METRIC, "value": r["evals_per_s"], "unit": "distance evals/s",
-               "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-               "dtype": "f32+bf16", "data": "synthetic",
-               "config": {"workload": f"serving_stream_{args.serve}req_{args.serve_rate:g}per_s"},
-               "latency": {"p50_s": r["p50_s"], "p99_s": r["p99_s"], "mean_s": r["mean_s"]},
-               "serving": r}
-        print(json.dumps(out), flush=True)
+        rates = [args.serve_rate]
+        if args.serve_protocol:
+            cap = serve_stream(args.serve, 0.0, args.serve_budget)
+            c = cap["completed_per_s"]
+            print(json.dumps({"serving_capacity": cap}), flush=True)
+            rates = [0.5 * c, 0.9 * c]
+        for rate in rates:
+            r = serve_stream(args.serve, rate, args.serve_budget)
+            out = {"metric": METRIC, "value": r["evals_per_s"], "unit": "distance evals/s",
+                   "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+                   "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+                   "config": {"workload": f"serving_stream_{args.serve}req_{rate:g}per_s"},
+                   "latency": {"p50_s": r["p50_s"], "p99_s": r["p99_s"], "mean_s": r["mean_s"]},
+                   "serving": r}
+            print(json.dumps(out), flush=True)
         return 0
     if args.copy_calibration:
         import torch

@@ -1810,6 +1810,12 @@ __device__ __forceinline__ void load8_f64(const T* __restrict__ row, int t0, int
   }
 }
 
+// Sum over the 64 lanes of a wave (xor butterfly).
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 // A copy of v the compiler must keep in a VGPR: with the key mask in an SGPR,
 // a key is then one v_and_or_b32 (one scalar operand per VALU instruction).
 __device__ __forceinline__ int opaque_vgpr(int v) {
@@ -2728,85 +2734,147 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
   block_sum_J(0.0, nfull, ncand, Jpart, upart);
 }
 
-// The FP64 re-rank of the points the screen marked (label -1): for each, the
-// nearest of its (at most four) candidates by the direct form sum (x - c)^2 in
-// FP64, lowest index among equal distances.  A wave reads 64 labels at a time;
-// groups of 16 lanes take the marked points four at a time (eight dims per
-// lane, the row and every candidate row requested before any is summed).
+// The re-rank of the points the screen marked (label -1): for each, the
+// nearest of its (at most four) candidates by the direct form sum (x - c)^2,
+// lowest index among equal distances.  A block takes ranges of RB points: its
+// threads list the marked ones in LDS, then groups of 16 lanes take one listed
+// point each (eight dims per lane; the row and every candidate row requested
+// before any is summed).  The distances are FP32 first, with the error bound of
+// the FP32 direct form; a point whose best two are closer than that bound is
+// decided in FP64.
 template <typename T, int KS>
 __global__ __launch_bounds__(256) void k_rerank_list(
-    const T* __restrict__ X, int64_t n, int d, int k, const double* __restrict__ c64,
+    const T* __restrict__ X, int64_t n, int d, int k, const float* __restrict__ cw,
+    const double* __restrict__ c64, const PassState* __restrict__ st,
     const int32_t* __restrict__ gate, int32_t* __restrict__ labels,
-    const int4* __restrict__ rq_c) {
+    const int4* __restrict__ rq_c, long long* __restrict__ upart) {
   if (gated(gate)) return;
+  constexpr int RB = 4096;                    // points per block range
   constexpr int NS8 = (KS * 16 + 127) / 128;  // 128-dim chunks of a row
-  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  __shared__ uint16_t list[RB];
+  __shared__ int cnt;
+  const int li = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const bool vec = (d & 7) == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  for (int64_t w0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; w0 < n; w0 += nw * 64) {
-    const int64_t i = w0 + lane;
-    unsigned long long m = __ballot(i < n && labels[i] < 0);
-    while (m) {
-      // the next four marked points of these 64: group g takes the g-th
-      int64_t pt = -1;
-      unsigned long long mm = m;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (mm) {
-          const int b = __ffsll((long long)mm) - 1;
-          mm &= mm - 1ull;
-          if (q == g) pt = w0 + b;
-        }
-      }
-      m = mm;
-      const bool act = pt >= 0;
-      const int4 cj = act ? rq_c[pt] : make_int4(-1, -1, -1, -1);
-      // (defensively, an index outside [0, k) is no candidate)
-      auto ok = [&](int j) { return (j >= 0 && j < k) ? j : -1; };
+  const bool cvec = (d & 3) == 0;
+  // FP32 direct form over a lane's <= 8 NS8 terms and four pairwise adds,
+  // plus 2 sqrt(D) ||c - cw|| for the rounded center
+  const float u32 = 0x1p-24f * 1.01f;
+  const float cmax = st->cmax;
+  auto err = [&](float D) {
+    return (float)(8 * NS8 + 6) * u32 * D + 2.f * sqrtf(D) * u32 * cmax + 1e-30f;
+  };
+  int64_t nfp64 = 0;
+  for (int64_t r0 = (int64_t)blockIdx.x * RB; r0 < n; r0 += (int64_t)gridDim.x * RB) {
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int rn = (int)min<int64_t>(RB, n - r0);
+    for (int o = threadIdx.x; o < rn; o += 256)
+      if (labels[r0 + o] < 0) list[atomicAdd(&cnt, 1)] = (uint16_t)o;
+    __syncthreads();
+    const int m = cnt;
+    // the 16 lanes of a group take the same q (uniform loop within a group)
+    for (int q = grp; q < m; q += 16) {
+      const int64_t pt = r0 + list[q];
+      const int4 cj = rq_c[pt];
+      auto ok = [&](int j) { return (j >= 0 && j < k) ? j : -1; };  // defensively
       const int cand[4] = {ok(cj.x), ok(cj.y), ok(cj.z), ok(cj.w)};
-      const T* xr = X + (act ? pt : 0) * d;
-      double part[4] = {0.0, 0.0, 0.0, 0.0};
+      const T* xr = X + pt * d;
+      float xv[NS8][8];
+      float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s8 = 0; s8 < NS8; ++s8) {
         const int t0 = 128 * s8 + 8 * li;
-        if (act && t0 < d) {
-          double xv[8];
-          load8_f64<T>(xr, t0, d, vec, xv);
-          double cv[4][8];
+        double xd[8];
+        load8_f64<T>(xr, t0, d, vec, xd);  // zero past d
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const double* cr = c64 + (int64_t)(cand[u] >= 0 ? cand[u] : 0) * d + t0;
+        for (int e8 = 0; e8 < 8; ++e8) xv[s8][e8] = (float)xd[e8];  // exact
+        float cv[4][8];
 #pragma unroll
-            for (int e8 = 0; e8 < 8; ++e8) cv[u][e8] = (cand[u] >= 0 && t0 + e8 < d) ? cr[e8] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u) {
+          const float* cr = cw + (int64_t)(cand[u] >= 0 ? cand[u] : 0) * d + t0;
+          if (cand[u] >= 0 && cvec && t0 + 8 <= d) {
+            const float4 a = *reinterpret_cast<const float4*>(cr);
+            const float4 b = *reinterpret_cast<const float4*>(cr + 4);
+            cv[u][0] = a.x; cv[u][1] = a.y; cv[u][2] = a.z; cv[u][3] = a.w;
+            cv[u][4] = b.x; cv[u][5] = b.y; cv[u][6] = b.z; cv[u][7] = b.w;
+          } else {
 #pragma unroll
             for (int e8 = 0; e8 < 8; ++e8)
-              if (t0 + e8 < d) {
-                const double diff = xv[e8] - cv[u][e8];
-                part[u] = __builtin_fma(diff, diff, part[u]);
-              }
+              cv[u][e8] = (cand[u] >= 0 && t0 + e8 < d) ? cr[e8] : 0.f;
+          }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int e8 = 0; e8 < 8; ++e8)
+            if (t0 + e8 < d) {
+              const float diff = xv[s8][e8] - cv[u][e8];
+              part[u] = __builtin_fmaf(diff, diff, part[u]);
+            }
       }
-      double bD = INFINITY;
-      int bj = INT_MAX;
+      float best = INFINITY, sec = INFINITY;
+      int bj = INT_MAX, nc = 0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        double v = part[u];  // the 16 lanes' parts (every lane takes part)
+        float v = part[u];
         v += __shfl_xor(v, 8);
         v += __shfl_xor(v, 4);
         v += __shfl_xor(v, 2);
         v += __shfl_xor(v, 1);
         const int j = cand[u];
-        if (j >= 0 && (v < bD || (v == bD && j < bj))) {
-          bD = v;
+        if (j < 0) continue;
+        ++nc;
+        if (v < best || (v == best && j < bj)) {
+          sec = best;
+          best = v;
           bj = j;
+        } else if (v < sec) {
+          sec = v;
         }
       }
-      if (act && li == 0) labels[pt] = bj < k ? bj : 0;
+      if (!(nc <= 1 || (sec - best) > err(best) + err(sec))) {
+        // too close for FP32: FP64 over the candidates
+        double bD = INFINITY;
+        int bj64 = INT_MAX;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = cand[u];
+          double p = 0.0;
+          if (j >= 0) {
+            const double* cr = c64 + (int64_t)j * d;
+#pragma unroll
+            for (int s8 = 0; s8 < NS8; ++s8) {
+              const int t0 = 128 * s8 + 8 * li;
+#pragma unroll
+              for (int e8 = 0; e8 < 8; ++e8)
+                if (t0 + e8 < d) {
+                  const double diff = (double)xv[s8][e8] - cr[t0 + e8];
+                  p = __builtin_fma(diff, diff, p);
+                }
+            }
+          }
+          p += __shfl_xor(p, 8);
+          p += __shfl_xor(p, 4);
+          p += __shfl_xor(p, 2);
+          p += __shfl_xor(p, 1);
+          if (j >= 0 && (p < bD || (p == bD && j < bj64))) {
+            bD = p;
+            bj64 = j;
+          }
+        }
+        bj = bj64;
+        if (li == 0) ++nfp64;
+      }
+      if (li == 0) labels[pt] = bj < k ? bj : 0;
     }
+    __syncthreads();  // the list is rebuilt for the next range
   }
+  // points decided in FP64 (the per-block counter of the FP64 checks of the pass)
+  nfp64 = wave_sum_i64(nfp64);
+  __shared__ long long wsum[4];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = nfp64;
+  __syncthreads();
+  if (threadIdx.x == 0 && upart) upart[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
 }
 
 // The re-screen of the points the screen queued: every center whose screened
@@ -3826,11 +3894,12 @@ static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* g
 template <typename T>
 static void dispatch_rerank(const PassBufs& b, const PassPlan& p, const int32_t* gate,
                             hipStream_t s) {
-  // a wave per 64 points, up to 4096 blocks (16 waves per SIMD on 256 CUs)
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 255) / 256, 4096));
+  // ranges of 4096 points, one block each (up to 2048 blocks in the grid)
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 4095) / 4096, 2048));
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, (const T*)b.X, b.n, b.d, b.k,
-                       (const double*)b.c64, gate, b.labels, (const int4*)b.rq_c);
+                       (const float*)b.cw, (const double*)b.c64, (const PassState*)b.st, gate,
+                       b.labels, (const int4*)b.rq_c, (long long*)nullptr);
   };
   if (p.ks <= 8) go(k_rerank_list<T, 8>);
   else go(k_rerank_list<T, 16>);
