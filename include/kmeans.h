@@ -233,12 +233,15 @@ km_status km_probe_mfma_bf16(int32_t iters, double* tflops, void* stream);
  * Many independent problems at once.  Each request is the two-stage method of
  * kmeans_fit on its own data; the passes of all requests advance together,
  * one launch per kernel for all of them (a batched pass), so that many small
- * problems share the GPU instead of each paying its own launches.  The batched
- * path scores distances in FP32 with the same certified error bound and FP64
- * check as kmeans_fit's FP32 kernels (for FP32 and BF16 data alike), keeps
- * exact 64-bit integer cluster sums, and supports d <= 128.  Its register tile
- * (points per thread, centers per LDS tile) comes from a built-in autotuner,
- * measured once per (dtype, d bucket, k bucket) and cached for the process.
+ * problems share the GPU instead of each paying its own launches.  FP32 data,
+ * and BF16 data with d <= 16, are scored in FP32 with the same certified error
+ * bound and FP64 check as kmeans_fit's FP32 kernels; BF16 data with
+ * 16 < d <= 128 and k <= 256 on BF16 matrix cores against -2c kept as two BF16
+ * parts, with a certified band and FP64 decisions among the candidates inside
+ * it.  Labels equal the FP64 argmin except at FP64 ties.  Cluster sums are
+ * exact 64-bit integers; d <= 128.  The FP32 kernel's register tile (points
+ * per thread, centers per LDS tile) comes from a built-in autotuner, measured
+ * once per (dtype, d bucket, k bucket) and cached for the process.
  * ------------------------------------------------------------------------- */
 typedef struct {
   const void* X;          /* n*d elements, row-major: device memory, or host memory with */
@@ -265,7 +268,9 @@ typedef struct {
 /* Fits count problems.  X, centers_out and labels_out are device pointers
    (x_on_host must be 0).  results: host, count entries.  Returns KM_OK when
    every problem was attempted; per-problem errors are in results[i].status.
-   Blocks until all results are in place.  stream: hipStream_t or NULL. */
+   Blocks until all results are in place.  stream: hipStream_t or NULL.
+   Passes run in chunks of up to 8 between host synchronisations, as in the
+   server (passes_per_sync below). */
 km_status kmeans_fit_batch(const km_request* reqs, int32_t count, km_result* results,
                            void* stream);
 
@@ -289,6 +294,12 @@ typedef struct {
   int32_t max_active;       /* problems advanced together, <= 8192 (0: 4096) */
   int32_t max_pending;      /* submitted, not yet admitted (0: 1 << 20); beyond: KM_EBUSY */
   int32_t use_graphs;       /* 1: replay captured HIP graphs of the batched pass */
+  /* Batched passes run back to back between two host synchronisations (0: 4,
+     at most 16).  A chunk never holds more passes than any admitted problem
+     may still need to reach its stage's max_iter; a problem whose stage stops
+     earlier (tol) is skipped by the device for the rest of the chunk.  New
+     problems join, and finished ones leave, between chunks. */
+  int32_t passes_per_sync;
 } km_server_cfg;
 
 typedef struct {
@@ -297,6 +308,7 @@ typedef struct {
   int64_t active, pending;     /* now */
   size_t bytes_in_use, peak_bytes;
   int64_t peak_active;
+  int64_t syncs;               /* host synchronisations: chunks of passes run */
 } km_server_counters;
 
 typedef struct km_server km_server;

@@ -86,7 +86,8 @@ class km_result(ctypes.Structure):
 
 class km_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
-                ("max_pending", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+                ("max_pending", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("passes_per_sync", ctypes.c_int32)]
 
 
 class km_server_counters(ctypes.Structure):
@@ -94,7 +95,8 @@ class km_server_counters(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("rounds", ctypes.c_int64), ("active", ctypes.c_int64),
                 ("pending", ctypes.c_int64), ("bytes_in_use", ctypes.c_size_t),
-                ("peak_bytes", ctypes.c_size_t), ("peak_active", ctypes.c_int64)]
+                ("peak_bytes", ctypes.c_size_t), ("peak_active", ctypes.c_int64),
+                ("syncs", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -455,10 +457,11 @@ class Server:
     footprint and advance together in batched passes; submit returns a ticket."""
 
     def __init__(self, hbm_budget_bytes: int = 0, max_active: int = 0, max_pending: int = 0,
-                 use_graphs: bool = True):
+                 use_graphs: bool = True, passes_per_sync: int = 0):
         cfg = km_server_cfg()
         cfg.hbm_budget_bytes, cfg.max_active = hbm_budget_bytes, max_active
         cfg.max_pending, cfg.use_graphs = max_pending, int(use_graphs)
+        cfg.passes_per_sync = passes_per_sync
         self._h = ctypes.c_void_p()
         _check(load().km_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._outs = {}

@@ -341,6 +341,15 @@ __device__ __forceinline__ double bf16_err(uint16_t b, double c) {
   return (double)__uint_as_float((uint32_t)b << 16) + 2.0 * c;
 }
 
+// -2c as a sum of two BF16 values hi + lo (hi = -2c rounded, lo = the rest
+// rounded); returns the error hi + lo + 2c.
+__device__ __forceinline__ double bf16_split(double c, uint16_t& hi, uint16_t& lo) {
+  hi = f32_to_bf16((float)(-2.0 * c));
+  const double h = (double)__uint_as_float((uint32_t)hi << 16);
+  lo = f32_to_bf16((float)(-2.0 * c - h));
+  return h + (double)__uint_as_float((uint32_t)lo << 16) + 2.0 * c;
+}
+
 // Publishes a block's squared rounding-error norm into the running maximum
 // (non-negative floats order as their bits); rounded up so that the stored
 // bound is not below the exact norm.
@@ -689,7 +698,22 @@ template <typename T>
 __device__ __forceinline__ double dist64_row(const T* __restrict__ xr,
                                              const double* __restrict__ c, int d) {
   double D = 0.0;
-  for (int t = 0; t < d; ++t) {
+  int t = 0;
+  // eight loads in flight, then the adds in the same order
+  for (; t + 8 <= d; t += 8) {
+    double cv[8], xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      cv[u] = c[t + u];
+      xv[u] = (double)widen<T>(xr[t + u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double diff = xv[u] - cv[u];
+      D = D + diff * diff;
+    }
+  }
+  for (; t < d; ++t) {
     const double diff = (double)widen<T>(xr[t]) - c[t];
     D = D + diff * diff;
   }
@@ -2483,9 +2507,25 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
   const int rot = (int)(blockIdx.x % (unsigned)nst);
   auto next_stage = [&](int gs) { return gs + 1 < nst ? gs + 1 : 0; };
   if ((int64_t)blockIdx.x * per_block < n) issue_stage(rot, cb0, bb0);
+  // The wave's rows of a batch, as the MFMAs' B operands.  BF16 data: loaded
+  // at the end of the previous batch, before its merges and candidate work, so
+  // that the loads' latency hides behind that work (the accumulators are free
+  // by then); FP32 data is rounded as it is loaded, at the start of the batch.
+  constexpr bool EARLY = sizeof(T) == 2;
+  v8bf x[PT][KS];
+  auto load_rows = [&](int64_t b0) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int64_t e = b0 + (int64_t)(wave * PT + p) * 32 + pc;
+      const bool ok = e < n;
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        x[p][s] = load8_bf16<T>(X + (ok ? e : 0) * d, 16 * s + 8 * h, d, ok);
+    }
+  };
+  if constexpr (EARLY) load_rows((int64_t)blockIdx.x * per_block);
   for (int64_t base = (int64_t)blockIdx.x * per_block; base < n;
        base += (int64_t)gridDim.x * per_block) {
-    v8bf x[PT][KS];
     int64_t ip[PT];
     bool valid[PT];
     float xn[PT], xr[PT];
@@ -2496,17 +2536,33 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
       valid[p] = e < n;
       ip[p] = valid[p] ? e : 0;
       float s2 = 0.f, r2 = 0.f;
+      if constexpr (EARLY) {
+        // ||x^||^2 by BF16 dot products (FP32 accumulation), two dims per step
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        x[p][s] = load8_bf16<T>(X + ip[p] * d, 16 * s + 8 * h, d, valid[p], r2);
-        const uint4 w = __builtin_bit_cast(uint4, x[p][s]);
-        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+        for (int s = 0; s < KS; ++s) {
+          const uint4 w = __builtin_bit_cast(uint4, x[p][s]);
+          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          s2 = __builtin_fmaf(bf16_lo(w4[u]), bf16_lo(w4[u]), s2);
-          s2 = __builtin_fmaf(bf16_hi(w4[u]), bf16_hi(w4[u]), s2);
+          for (int u = 0; u < 4; ++u) {
+            const bf16x2 v = __builtin_bit_cast(bf16x2, w4[u]);
+            s2 = __builtin_amdgcn_fdot2_f32_bf16(v, v, s2, false);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          x[p][s] = load8_bf16<T>(X + ip[p] * d, 16 * s + 8 * h, d, valid[p], r2);
+          const uint4 w = __builtin_bit_cast(uint4, x[p][s]);
+          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            s2 = __builtin_fmaf(bf16_lo(w4[u]), bf16_lo(w4[u]), s2);
+            s2 = __builtin_fmaf(bf16_hi(w4[u]), bf16_hi(w4[u]), s2);
+          }
         }
       }
+      // (the 1% covers the rounding of the FP32 sums and of the square root)
       xn[p] = sqrtf(s2 + __shfl_xor(s2, 32)) * 1.01f;
       xr[p] = sqrtf(r2 + __shfl_xor(r2, 32)) * 1.01f;
 #pragma unroll
@@ -2608,8 +2664,12 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
       gs = gs2;
     }
     keys(accP, ctP);
-    // both buffers are free: the next tile's first stage loads during the re-rank
-    if (base + (int64_t)gridDim.x * per_block < n) issue_stage(rot, cb0, bb0);
+    // both buffers are free: the next batch's first stage and (BF16 data) rows
+    // load during the merges below
+    if (base + (int64_t)gridDim.x * per_block < n) {
+      issue_stage(rot, cb0, bb0);
+      if constexpr (EARLY) load_rows(base + (int64_t)gridDim.x * per_block);
+    }
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
       // Two scores differ from their exact values (||c||^2 + B - 2 x.c) by at most
@@ -3104,7 +3164,7 @@ __device__ void finalize_center(
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
     double* __restrict__ J_hist, double* __restrict__ shift_hist, bool mark_labelled = false,
     bool biased = false, double* __restrict__ trace_c = nullptr,
-    long long* __restrict__ trace_n = nullptr) {
+    long long* __restrict__ trace_n = nullptr, uint16_t* __restrict__ cb16lo = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t C = (int64_t)k * (d + 1);
   // this pass's index in the stage (the last block of the pass advances it
@@ -3155,7 +3215,13 @@ __device__ void finalize_center(
         nn += cnew * cnew;
         c64[(int64_t)j * d + t] = cnew;
         cw[(int64_t)j * d + t] = (float)cnew;
-        if (cb16) {
+        if (cb16lo) {
+          uint16_t hi, lo;
+          const double e = bf16_split(cnew, hi, lo);
+          cb16[cb16_at(j, t, kd16)] = hi;
+          cb16lo[cb16_at(j, t, kd16)] = lo;
+          ee += e * e;
+        } else if (cb16) {
           const uint16_t b = f32_to_bf16((float)(-2.0 * cnew));
           cb16[cb16_at(j, t, kd16)] = b;
           const double e = bf16_err(b, cnew);
@@ -3393,12 +3459,15 @@ __global__ __launch_bounds__(256) void k_sum_J(PassState* __restrict__ st,
 // ============================================================================
 // The instance owning entry u: the last one whose first entry is <= u (every
 // listed instance has at least one entry).
+// which: 0 assignment units, 1 finalize entries, 2 cluster-sum units (an
+// instance without sum units shares its first entry with the next one and is
+// never the last such).
 __device__ __forceinline__ int batch_find(const BatchInst* __restrict__ bi, int ninst, int64_t u,
-                                          bool centers) {
+                                          int which) {
   int lo = 0, hi = ninst;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    const int64_t s0 = centers ? bi[mid].center0 : bi[mid].unit0;
+    const int64_t s0 = which == 1 ? bi[mid].center0 : which == 2 ? bi[mid].sunit0 : bi[mid].unit0;
     if (s0 <= u) lo = mid;
     else hi = mid;
   }
@@ -3418,7 +3487,7 @@ __global__ __launch_bounds__(256) void k_batch_assign(const BatchHead* __restric
   const int ninst = hd->ninst;
   const int64_t units = hd->units;
   for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    const BatchInst& b = bi[batch_find(bi, ninst, u, false)];
+    const BatchInst& b = bi[batch_find(bi, ninst, u, 0)];
     PassState* st = b.st;
     const int dn = ld_agent(&st->done);
     if ((b.mode == 1 && dn) || (b.mode == 2 && dn == 2)) continue;
@@ -3436,8 +3505,8 @@ __global__ __launch_bounds__(256) void k_batch_assign(const BatchHead* __restric
           smem + (((size_t)ktile * (DMAX + 1) * 4 + 15) / 16) * 16);
       for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
       __syncthreads();
-    } else if (b.mode == 1) {
-      S = row;
+    } else if (b.mode == 1 && b.sunits == 0) {
+      S = row;  // otherwise k_batch_sums adds them after the labels are written
     }
     double Jacc = 0.0;
     int64_t ucnt = 0;
@@ -3455,6 +3524,462 @@ __global__ __launch_bounds__(256) void k_batch_assign(const BatchHead* __restric
   }
 }
 
+// The batched BF16 screen: one launch scores the points of every listed
+// BF16 instance with d in (16, 16 KS] and k <= 256 on the matrix cores.  A work
+// unit is a tile of 256 points of one instance; each wave takes 64 of them as
+// two 32-point MFMA B operands (x.c^T as 32x32x16 BF16 MFMAs, FP32
+// accumulation from the C input ||c||^2 + B), reading the instance's copy of
+// -2c as two BF16 parts hi + lo (tiled as in the single-problem screen: the 32
+// rows of one MFMA operand are 512 contiguous bytes) straight from memory.
+// BF16 data is exact, so a score's error is that of hi + lo (about 2^-17 of
+// |c|) and of the FP32 accumulation: the band stays narrow even when the
+// points lie far from the origin compared with the clusters' spread.  Each lane keeps the best four keys of its half of every
+// tile's centers; the halves merge into the point's best four.  The error
+// band of two scores (the centers' exact rounding error norm dcn, the FP32
+// accumulation) certifies the best; when two or three keys lie inside it and
+// the fourth does not, FP64 distances decide among them; otherwise the wave's
+// FP64 check over all centers decides.  Then J (FP64 direct form), the label
+// and (when they fit in LDS) the exact cluster sums, as in the FP32 batched
+// kernel; larger sums are added by k_batch_sums from the labels.
+template <int KS>
+__global__ __launch_bounds__(256, 2) void k_batch_screen(const BatchHead* __restrict__ hd,
+                                                      const BatchInst* __restrict__ bi) {
+  constexpr int KD = KS * 16;
+  constexpr int C8 = KD / 8;     // 16-byte chunks per center row of the copy
+  constexpr int BG = 8;          // index bits of a key (k <= 256)
+  constexpr int GM = (1 << BG) - 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31;
+  const int wave = threadIdx.x >> 6;
+  const int ninst = hd->ninst;
+  const int64_t units = hd->units;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const BatchInst& b = bi[batch_find(bi, ninst, u, 0)];
+    PassState* st = b.st;
+    const int dn = ld_agent(&st->done);
+    if ((b.mode == 1 && dn) || (b.mode == 2 && dn == 2)) continue;
+    const int64_t tile = u - b.unit0;
+    const int d = b.d, k = b.k, nct = (k + 31) >> 5;
+    const uint16_t* X = reinterpret_cast<const uint16_t*>(b.X);
+    const uint16_t* cb = b.cb16;
+    const uint16_t* cbl = b.cb16lo;
+    const float* cnB = b.cnB;
+    const int64_t n = b.n;
+    unsigned long long* S = nullptr;
+    const bool lds = b.mode == 1 && b.lds_sums;
+    const int slot = (int)(tile & (kSlots - 1));
+    unsigned long long* row =
+        reinterpret_cast<unsigned long long*>(b.slots + (int64_t)slot * k * (d + 1));
+    if (lds) {
+      S = reinterpret_cast<unsigned long long*>(smem);
+      for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
+      __syncthreads();
+    } else if (b.mode == 1 && b.sunits == 0) {
+      S = row;  // otherwise k_batch_sums adds them after the labels are written
+    }
+    // the wave's 64 points: tile A (points 0..31) and tile B (32..63) of its part
+    const int64_t p0 = tile * 256 + (int64_t)wave * 64;
+    const int64_t iA = p0 + pc, iB = p0 + 32 + pc;
+    const bool vA = iA < n, vB = iB < n;
+    v8bf xA[KS], xB[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      xA[s] = load8_bf16<uint16_t>(X + (vA ? iA : 0) * d, 16 * s + 8 * h, d, vA);
+      xB[s] = load8_bf16<uint16_t>(X + (vB ? iB : 0) * d, 16 * s + 8 * h, d, vB);
+    }
+    const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f;
+    // FP32 accumulation of 2 KD products and the bias, any rounding of the
+    // partial sums
+    const float ea = (float)(2 * KD + 8) * 0x1p-23f * 1.01f;
+    const float delta = (float)(1 << BG) * 0x1p-23f * 1.01f;
+    // the four smallest keys of the lane's scores, ascending
+    int ga[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX}, gb[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+    auto insert = [](int (&m)[4], int kv) {
+      m[3] = med3_i32(m[2], kv, m[3]);
+      m[2] = med3_i32(m[1], kv, m[2]);
+      m[1] = med3_i32(m[0], kv, m[1]);
+      m[0] = min(m[0], kv);
+    };
+    auto rank = [&](const v16f& acc, int t, int (&m)[4]) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int j = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
+        insert(m, (__float_as_int(acc[r]) & ~GM) | j);
+      }
+    };
+    // A operands (hi and lo parts) and C input of center tile t (rows 32t ..
+    // 32t + 31 of the copy)
+    auto load_a = [&](int t, v8bf (&a)[KS], v8bf (&al)[KS], v16f& bias) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int64_t o = ((int64_t)(t * C8 + 2 * s + h) * 32 + pc) * 8;
+        a[s] = *reinterpret_cast<const v8bf*>(cb + o);
+        al[s] = *reinterpret_cast<const v8bf*>(cbl + o);
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 v = *reinterpret_cast<const float4*>(cnB + 32 * t + 8 * g + 4 * h);
+        bias[4 * g] = v.x; bias[4 * g + 1] = v.y; bias[4 * g + 2] = v.z; bias[4 * g + 3] = v.w;
+      }
+    };
+    v8bf a[KS], al[KS];
+    v16f bias;
+    for (int t = 0; t < nct; ++t) {
+      load_a(t, a, al, bias);
+      v16f accA = bias, accB = bias;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xA[s], accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xB[s], accB, 0, 0, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xA[s], accA, 0, 0, 0);
+        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xB[s], accB, 0, 0, 0);
+      }
+      rank(accA, t, ga);
+      rank(accB, t, gb);
+    }
+    // merge the lane halves: both lanes of a point get its best four keys
+    auto merge_halves = [&](int (&m)[4]) {
+      int o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = __shfl_xor(m[q], 32);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) insert(m, o[q]);
+    };
+    merge_halves(ga);
+    merge_halves(gb);
+    double Jacc = 0.0;
+    int64_t ucnt = 0, pcnt = 0;
+    // Decisions of the wave's two points per lane pair (tile A's, tile B's):
+    // the band E2 of two scores, the tracked keys inside the band of the best
+    // (nc: the band grows with the score, so they are a prefix), and
+    //   certain: only the best inside;
+    //   pair: two or three inside, all real centers, the fourth outside: FP64
+    //         decides among them;
+    //   full: otherwise.  A full point's candidates are every center whose
+    //         score is within thr of the best (a second pass over the centers
+    //         collects them, up to kBatchCands); FP64 decides among them, or
+    //         over all centers when there are more.
+    constexpr int kBatchCands = 16;
+    __shared__ uint8_t cand[4][2][32][kBatchCands];
+    __shared__ int ccnt[4][2][32];
+    bool pairv[2], fullv[2];
+    int ncv[2], best[2];
+    float thr[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const v8bf* x = p == 0 ? xA : xB;
+      const bool valid = p == 0 ? vA : vB;
+      int g[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[q] = p == 0 ? ga[q] : gb[q];
+      // ||x||^2 of the point (BF16 data: the MFMA sees x exactly)
+      float s2 = 0.f;
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const uint4 w = __builtin_bit_cast(uint4, x[s]);
+        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bf16x2 v = __builtin_bit_cast(bf16x2, w4[q]);
+          s2 = __builtin_amdgcn_fdot2_f32_bf16(v, v, s2, false);
+        }
+      }
+      const float xn = sqrtf(s2 + __shfl_xor(s2, 32)) * 1.01f;
+      const float E2 = 2.f * xn * dcn + 2.f * ea * (cmax * cmax + B + 2.f * xn * cmax);
+      auto apart = [&](float lo, float hi) {
+        return (hi - lo) > E2 + delta * (fabsf(hi) + fabsf(lo));
+      };
+      const float v1 = __int_as_float(g[0] & ~GM);
+      int nc = 1;
+      bool real = (g[0] & GM) < k;
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        if (nc == q && !apart(v1, __int_as_float(g[q] & ~GM))) {
+          nc = q + 1;
+          real = real && (g[q] & GM) < k;
+        }
+      const bool certain = k == 1 || (real && nc == 1);
+      pairv[p] = valid && !certain && real && nc < 4;
+      fullv[p] = valid && !certain && !pairv[p];
+      ncv[p] = nc;
+      best[p] = (g[0] & GM) < k ? (g[0] & GM) : 0;
+      // a center whose exact distance is at most the best's scores at most
+      // E2 above the smallest score; the key of that score is within delta
+      thr[p] = (v1 + E2 + delta * (2.f * fabsf(v1) + E2)) * 1.0001f;
+    }
+    if (__ballot(fullv[0] || fullv[1])) {
+      if (h == 0) ccnt[wave][0][pc] = ccnt[wave][1][pc] = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      v8bf a[KS], al[KS];
+      v16f bias;
+      for (int t = 0; t < nct; ++t) {
+        load_a(t, a, al, bias);
+        v16f accA = bias, accB = bias;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xA[s], accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xB[s], accB, 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xA[s], accA, 0, 0, 0);
+          accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xB[s], accB, 0, 0, 0);
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          if (!fullv[p]) continue;
+          const v16f& acc = p == 0 ? accA : accB;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int j = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
+            if (j < k && acc[r] <= thr[p]) {
+              const int c = atomicAdd(&ccnt[wave][p][pc], 1);
+              if (c < kBatchCands) cand[wave][p][pc][c] = (uint8_t)j;
+            }
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const v8bf* x = p == 0 ? xA : xB;
+      const int64_t i = p == 0 ? iA : iB;
+      const bool valid = p == 0 ? vA : vB;
+      const bool pair = pairv[p];
+      const int nc = ncv[p];
+      int bi1 = best[p];
+      const int* gq = p == 0 ? ga : gb;
+      // FP64 direct form over the lane half's dims, then both halves'
+      auto dist64 = [&](int j) {
+        const double* cj = b.c64 + (int64_t)j * d;
+        double part = 0.0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const uint4 w = __builtin_bit_cast(uint4, x[s]);
+          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int t = 16 * s + 8 * h + q;
+            if (t < d) {
+              const float xv = (q & 1) ? bf16_hi(w4[q >> 1]) : bf16_lo(w4[q >> 1]);
+              const double e = (double)xv - cj[t];
+              part = __builtin_fma(e, e, part);
+            }
+          }
+        }
+        return part + __shfl_xor(part, 32);
+      };
+      if (__ballot(pair)) {
+        // FP64 distances of the candidates (lowest index on equal values)
+        double bd = dist64(bi1);
+#pragma unroll
+        for (int q = 1; q < 3; ++q) {
+          const bool use = pair && q < nc;
+          if (__ballot(use)) {
+            const int jq = use ? (gq[q] & GM) : bi1;
+            const double dq = dist64(jq);
+            if (use && (dq < bd || (dq == bd && jq < bi1))) {
+              bd = dq;
+              bi1 = jq;
+            }
+          }
+        }
+        pcnt += __popcll(__ballot(pair && h == 0));
+      }
+      const bool full = fullv[p];
+      if (__ballot(full)) {
+        const int cnt = full ? ccnt[wave][p][pc] : 0;
+        const bool listed = full && cnt >= 1 && cnt <= kBatchCands;
+        int qn = listed ? cnt : 0;
+        for (int o = 32; o > 0; o >>= 1) qn = max(qn, __shfl_xor(qn, o));
+        double bd = INFINITY;
+        int bj = INT_MAX;
+        for (int q = 0; q < qn; ++q) {
+          const bool use = listed && q < cnt;
+          const int jq = use ? (int)cand[wave][p][pc][q] : bi1;
+          const double dq = dist64(jq);
+          if (use && (dq < bd || (dq == bd && jq < bj))) {
+            bd = dq;
+            bj = jq;
+          }
+        }
+        if (listed) bi1 = bj < k ? bj : 0;
+        pcnt += __popcll(__ballot(listed && h == 0));
+        const bool rest = full && !listed;
+        if (__ballot(rest)) {
+          int lab = bi1;
+          ucnt += wave_fp64_fallback<uint16_t>(rest && h == 0, i, X, d, k, b.c64, lab);
+          // the half-0 lane decided: both halves take its label
+          lab = __shfl(lab, pc);
+          if (rest) bi1 = lab;
+        }
+      }
+      const double D = dist64(valid ? bi1 : 0);
+      if (valid && h == 0) {
+        Jacc += D;
+        if (b.labels) b.labels[i] = bi1;
+      }
+      if (valid && S) {
+        // exact sums: rint(x 2^F) of the lane half's dims; the count from half 0
+        unsigned long long* Sr = S + (int64_t)bi1 * (d + 1);
+        const float sc = st->scale;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const uint4 w = __builtin_bit_cast(uint4, x[s]);
+          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int t = 16 * s + 8 * h + q;
+            if (t < d) {
+              const float xv = (q & 1) ? bf16_hi(w4[q >> 1]) : bf16_lo(w4[q >> 1]);
+              const long long qv = (long long)__float2int_rn(xv * sc);
+              atomicAdd(&Sr[t], (unsigned long long)qv);
+            }
+          }
+        }
+        if (h == 0) atomicAdd(&Sr[d], 1ull);
+      }
+    }
+    if (lds) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < k * (d + 1); e += 256) {
+        const unsigned long long v = S[e];
+        if (v) atomicAdd(&row[e], v);
+      }
+    }
+    block_sum_J(Jacc, ucnt, pcnt, b.Jpart, b.upart, tile);
+  }
+}
+
+// Exact cluster sums of the listed instances whose sums do not fit in LDS,
+// from the labels the assignment launch wrote.  A work unit is a range of
+// kBatchSumPts points and a range of skc centers: the block adds the rows of
+// the points labelled inside its center range into an LDS table skc x (d+1)
+// (64-bit integer atomics), then adds the table's non-zero entries into the
+// instance's slot row.  Each point is read once, by the unit of its center
+// range; integer sums do not depend on the order.  A wave takes 64 labels at a
+// time and moves the selected points four at once (16 lanes a point, 8 dims a
+// lane), four such groups in flight.  Persistent: blocks loop over the units.
+__global__ __launch_bounds__(256) void k_batch_sums(const BatchHead* __restrict__ hd,
+                                                    const BatchInst* __restrict__ bi) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned long long* S = reinterpret_cast<unsigned long long*>(smem);
+  __shared__ int order[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane >> 4, sub = lane & 15;
+  const int ninst = hd->ninst;
+  const int64_t units = hd->units;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const BatchInst& b = bi[batch_find(bi, ninst, u, 2)];
+    PassState* st = b.st;
+    if (b.mode != 1 || ld_agent(&st->done)) continue;
+    const int d = b.d, k = b.k, kc = b.skc;
+    const int nkr = (k + kc - 1) / kc;
+    const int64_t local = u - b.sunit0;
+    const int64_t pb = local / nkr;
+    const int c0 = (int)(local - pb * nkr) * kc;
+    const int cn = min(kc, k - c0);
+    const int w = d + 1;
+    for (int e = threadIdx.x; e < cn * w; e += 256) S[e] = 0ull;
+    __syncthreads();
+    const int64_t i0 = pb * kBatchSumPts, i1 = min(b.n, i0 + kBatchSumPts);
+    const float sc = st->scale;
+    const bool bf = b.dtype == 1;
+    // whole 16-byte pieces of every row (8 BF16 or 2 x 4 FP32 dims)
+    const bool vec = (d & 7) == 0 && (reinterpret_cast<uintptr_t>(b.X) & 15) == 0;
+    const int32_t* lab = b.labels;
+    for (int64_t g = i0 + (int64_t)wave * 64; g < i1; g += 256) {
+      const int64_t i = g + lane;
+      const int l = i < i1 ? lab[i] : -1;
+      const bool sel = l >= c0 && l < c0 + cn;
+      const unsigned long long m = __ballot(sel);
+      const int cnt = __popcll(m);
+      if (cnt == 0) continue;
+      // the selected lanes in order: order[r] = lane of the r-th selected
+      const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+      if (sel) order[wave][rank] = lane;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int q0 = 0; q0 < cnt; q0 += 16) {
+        constexpr int R = 4;
+        long long qv[R][8];
+        int lp[R];
+        bool ok[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int qi = q0 + 4 * r + grp;
+          ok[r] = qi < cnt;
+          const int src = ok[r] ? order[wave][qi] : 0;
+          lp[r] = __shfl(l, src);
+          const int64_t row = (g + src) * d;
+          const int t0 = 8 * sub;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) qv[r][e] = 0;
+          if (ok[r] && t0 < d) {
+            float xv[8];
+            if (vec && bf) {
+              const uint4 v = *reinterpret_cast<const uint4*>(
+                  static_cast<const uint16_t*>(b.X) + row + t0);
+              const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                xv[2 * e] = bf16_lo(w4[e]);
+                xv[2 * e + 1] = bf16_hi(w4[e]);
+              }
+            } else if (vec) {
+              const float4 v0 = *reinterpret_cast<const float4*>(
+                  static_cast<const float*>(b.X) + row + t0);
+              const float4 v1 = *reinterpret_cast<const float4*>(
+                  static_cast<const float*>(b.X) + row + t0 + 4);
+              xv[0] = v0.x; xv[1] = v0.y; xv[2] = v0.z; xv[3] = v0.w;
+              xv[4] = v1.x; xv[5] = v1.y; xv[6] = v1.z; xv[7] = v1.w;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                const int t = t0 + e;
+                xv[e] = t >= d ? 0.f
+                        : bf ? __uint_as_float((uint32_t)static_cast<const uint16_t*>(b.X)[row + t]
+                                               << 16)
+                             : static_cast<const float*>(b.X)[row + t];
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) qv[r][e] = (long long)__float2int_rn(xv[e] * sc);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (!ok[r]) continue;
+          unsigned long long* Sr = S + (int64_t)(lp[r] - c0) * w;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (8 * sub + e < d) atomicAdd(&Sr[8 * sub + e], (unsigned long long)qv[r][e]);
+          if (sub == 0) atomicAdd(&Sr[d], 1ull);
+        }
+      }
+      // order[] is rewritten by the next group of labels
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    unsigned long long* row = reinterpret_cast<unsigned long long*>(
+        b.slots + (int64_t)(pb & (kSlots - 1)) * k * w + (int64_t)c0 * w);
+    for (int e = threadIdx.x; e < cn * w; e += 256) {
+      const unsigned long long v = S[e];
+      if (v) atomicAdd(&row[e], v);
+    }
+    __syncthreads();
+  }
+}
+
 // Finalize entries of every listed instance (one per center), persistent.  The
 // last entry of an instance concludes its pass (J, movement, stop test).
 __global__ __launch_bounds__(256) void k_batch_finalize(const BatchHead* __restrict__ hd,
@@ -3462,12 +3987,13 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const BatchHead* __restr
   const int ninst = hd->ninst;
   const int64_t centers = hd->centers;
   for (int64_t c = blockIdx.x; c < centers; c += gridDim.x) {
-    const BatchInst& b = bi[batch_find(bi, ninst, c, true)];
+    const BatchInst& b = bi[batch_find(bi, ninst, c, 1)];
     const int dn = ld_agent(&b.st->done);
     if ((b.mode == 1 && dn) || (b.mode == 2 && dn == 2)) continue;
     finalize_center((int)(c - b.center0), b.slots, nullptr, b.k, b.d, b.st, b.mode == 1 ? 1 : 0,
-                    b.c64, b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, nullptr, nullptr, nullptr,
-                    nullptr, 0, b.Jpart, b.upart, b.units, b.J_hist, b.shift_hist, b.mode == 2);
+                    b.c64, b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, nullptr, nullptr, b.cb16,
+                    b.cnB, b.kd16, b.Jpart, b.upart, b.units, b.J_hist, b.shift_hist,
+                    b.mode == 2, false, nullptr, nullptr, b.cb16lo);
   }
 }
 
@@ -3513,15 +4039,24 @@ __global__ __launch_bounds__(256) void k_fill_uniform(void* __restrict__ p, int6
 __global__ __launch_bounds__(64) void k_prep_bf16(const double* __restrict__ c64, int k, int d,
                                                   int kd16, PassState* __restrict__ st,
                                                   uint16_t* __restrict__ cb16,
-                                                  float* __restrict__ cnB) {
+                                                  float* __restrict__ cnB,
+                                                  uint16_t* __restrict__ cb16lo) {
   const int j = blockIdx.x, lane = threadIdx.x;
   double acc = 0.0, e2 = 0.0;
   for (int t = lane; t < kd16; t += 64) {
     const double c = (t < d && j < k) ? c64[(int64_t)j * d + t] : 0.0;
-    const uint16_t b = f32_to_bf16((float)(-2.0 * c));
-    cb16[cb16_at(j, t, kd16)] = b;
+    double e;
+    if (cb16lo) {
+      uint16_t hi, lo;
+      e = bf16_split(c, hi, lo);
+      cb16[cb16_at(j, t, kd16)] = hi;
+      cb16lo[cb16_at(j, t, kd16)] = lo;
+    } else {
+      const uint16_t b = f32_to_bf16((float)(-2.0 * c));
+      cb16[cb16_at(j, t, kd16)] = b;
+      e = bf16_err(b, c);
+    }
     acc += c * c;
-    const double e = bf16_err(b, c);
     e2 += e * e;
   }
   for (int o = 32; o > 0; o >>= 1) {
@@ -3541,9 +4076,9 @@ __global__ __launch_bounds__(64) void k_prep_bf16(const double* __restrict__ c64
 }
 
 hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, PassState* st,
-                     uint16_t* cb16, float* cnB, hipStream_t s) {
+                     uint16_t* cb16, float* cnB, hipStream_t s, uint16_t* cb16lo) {
   hipLaunchKernelGGL(k_prep_bf16, dim3((unsigned)bf16_rows(k)), dim3(64), 0, s, c64, k, d, kd16,
-                     st, cb16, cnB);
+                     st, cb16, cnB, cb16lo);
   return hipGetLastError();
 }
 
@@ -3998,9 +4533,25 @@ static bool visit_batch(int dmax, int ppt, F&& f) {
   return false;
 }
 
-int64_t batch_resident_blocks(int dtype, int dmax, int ppt, size_t lds, int cus) {
+int batch_screen_ks(int dtype, int32_t d, int32_t k) {
+  if (dtype != 1 || d <= 16 || d > 128 || k > 256) return 0;
+  return d <= 32 ? 2 : d <= 64 ? 4 : 8;
+}
+
+template <typename F>
+static bool visit_batch_screen(int ks, F&& f) {
+  switch (ks) {
+    case 2: f(k_batch_screen<2>); return true;
+    case 4: f(k_batch_screen<4>); return true;
+    case 8: f(k_batch_screen<8>); return true;
+    default: return false;
+  }
+}
+
+int64_t batch_resident_blocks(int dtype, int dmax, int ppt, size_t lds, int cus, int screen) {
   int64_t r = 0;
   auto f = [&](auto kern) { r = resident_blocks(kern, lds, cus); };
+  if (screen) return visit_batch_screen(screen, f) ? r : 0;
   const bool ok = dtype == 0 ? visit_batch<float>(dmax, ppt, f) : visit_batch<uint16_t>(dmax, ppt, f);
   return ok ? r : 0;
 }
@@ -4010,9 +4561,16 @@ hipError_t batch_assign(const BatchHead* hd, const BatchInst* bi, const BatchSha
   auto f = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)sh.blocks), dim3(256), sh.lds, s, hd, bi);
   };
-  const bool ok = sh.dtype == 0 ? visit_batch<float>(sh.dmax, sh.ppt, f)
-                                : visit_batch<uint16_t>(sh.dmax, sh.ppt, f);
+  const bool ok = sh.screen ? visit_batch_screen(sh.screen, f)
+                  : sh.dtype == 0 ? visit_batch<float>(sh.dmax, sh.ppt, f)
+                                  : visit_batch<uint16_t>(sh.dmax, sh.ppt, f);
   if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t batch_sums(const BatchHead* hd, const BatchInst* bi, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_sums, dim3((unsigned)std::max(1, blocks)), dim3(256),
+                     kBatchSumLds, s, hd, bi);
   return hipGetLastError();
 }
 

@@ -96,6 +96,15 @@ struct BatchInst {
   double* Jpart;         // [units]
   long long* upart;      // [2 * units]
   double* J_hist; double* shift_hist;  // optional, indexed by the pass
+  // BF16 screen instances (k_batch_screen): the tiled BF16 copy of -2c as
+  // hi + lo (bf16_rows(k) rows of kd16 dims each) and ||c||^2 + B; NULL for
+  // the FP32 kernel
+  uint16_t* cb16; float* cnB; int32_t kd16;
+  uint16_t* cb16lo;
+  // Lloyd passes whose sums do not fit in LDS: units of k_batch_sums (ranges of
+  // kBatchSumPts points x skc centers), 0 when the assignment adds the sums
+  int32_t skc;
+  int64_t sunit0, sunits;
 };
 struct BatchHead {
   int32_t ninst;
@@ -124,8 +133,9 @@ hipError_t stage_reset(PassState* st, hipStream_t s);
 hipError_t row_stats(const void* X, int dtype, int64_t rows, int32_t d, bool norms,
                      PassState* st, hipStream_t s);
 hipError_t zero_i64(long long* p, int64_t count, hipStream_t s);
+// cb16lo: when given, -2c is kept as hi + lo (the rest rounded to BF16 again)
 hipError_t prep_bf16(const double* c64, int32_t k, int32_t d, int kd16, PassState* st,
-                     uint16_t* cb16, float* cnB, hipStream_t s);
+                     uint16_t* cb16, float* cnB, hipStream_t s, uint16_t* cb16lo = nullptr);
 hipError_t prep_centers(const double* c64, int32_t k, int32_t d, float* cw, float* cn,
                         double* cnorm, hipStream_t s);
 hipError_t stage_begin(PassState* st, int32_t max_iter, double tol, int64_t rows,
@@ -192,11 +202,20 @@ struct BatchShape {
   int dtype, dmax, ppt;
   size_t lds;   // dynamic LDS of the assignment launch
   int blocks;   // persistent grid
+  int screen;   // K steps of the BF16 screen kernel (0: the FP32 kernel)
 };
+// The batched BF16 screen takes BF16 data with 16 < d <= 128 and k <= 256;
+// returns its K steps (2, 4 or 8), or 0.
+int batch_screen_ks(int dtype, int32_t d, int32_t k);
 int batch_dmax(int32_t d);                       // 0: d too large for the batched path
-int64_t batch_resident_blocks(int dtype, int dmax, int ppt, size_t lds, int cus);
+int64_t batch_resident_blocks(int dtype, int dmax, int ppt, size_t lds, int cus,
+                              int screen = 0);
 hipError_t batch_assign(const BatchHead* hd, const BatchInst* bi, const BatchShape& sh,
                         hipStream_t s);
+// Cluster sums of the instances with sum units (after the assignment launches).
+constexpr int64_t kBatchSumPts = 8192;
+constexpr size_t kBatchSumLds = 65536;
+hipError_t batch_sums(const BatchHead* hd, const BatchInst* bi, int blocks, hipStream_t s);
 hipError_t batch_finalize(const BatchHead* hd, const BatchInst* bi, int blocks, hipStream_t s);
 hipError_t batch_status(const BatchHead* hd, const BatchInst* bi, BatchStatus* out,
                         hipStream_t s);

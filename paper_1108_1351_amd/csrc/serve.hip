@@ -25,6 +25,7 @@ constexpr int kMaxShapes = 16;        // register-tile shapes live in one engine
 constexpr int kTableCap = 8192;       // problems advanced together
 constexpr size_t kSumsLds = 32768;    // LDS for privatised cluster sums in the batched kernel
 constexpr int kFinalizeBlocks = 1024;
+constexpr int kMaxChunk = 16;         // passes between two host synchronisations
 
 // ------------------------------------------------------------------ autotuner
 struct TuneKey {
@@ -196,6 +197,13 @@ struct Job {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int64_t unc2 = 0;  // FP64 checks counted by the slow stage's passes
   int64_t passed_over = 0;  // admission rounds in which later problems went ahead
+  int32_t iter_now = 0;     // passes run in the current stage, from the last status
+  // BF16 data with 16 < d <= 128 and k <= 256: the batched BF16 screen (its K
+  // steps), with the tiled BF16 copy of -2c and ||c||^2 + B
+  int screen = 0;
+  uint16_t* cb16 = nullptr;
+  uint16_t* cb16lo = nullptr;
+  float* cnB = nullptr;
 };
 
 // Admission rounds a waiting problem may be passed by later, smaller ones;
@@ -239,7 +247,9 @@ size_t job_layout(Job& j, void* base) {
                o_slots = c.take<long long>((size_t)kSlots * k * (d + 1)),
                o_lab = c.take<int32_t>(r.labels_out ? 0 : (size_t)n),
                o_jp = c.take<double>((size_t)units), o_up = c.take<long long>((size_t)units * 2),
-               o_x = c.take<unsigned char>(j.copy_x ? (size_t)n * d * elt_size(r.dtype) : 0);
+               o_x = c.take<unsigned char>(j.copy_x ? (size_t)n * d * elt_size(r.dtype) : 0),
+               o_cb = c.take<uint16_t>(j.screen ? (size_t)bf16_rows(k) * 16 * j.screen * 2 : 0),
+               o_cnb = c.take<float>(j.screen ? (size_t)bf16_rows(k) : 0);
   if (base) {
     j.sel = at<SelState>(base, o_sel);
     j.hist = at<unsigned long long>(base, o_hist);
@@ -260,6 +270,9 @@ size_t job_layout(Job& j, void* base) {
     j.jpart = at<double>(base, o_jp);
     j.upart = at<long long>(base, o_up);
     j.X = j.copy_x ? (const void*)at<unsigned char>(base, o_x) : r.X;
+    j.cb16 = j.screen ? at<uint16_t>(base, o_cb) : nullptr;
+    j.cb16lo = j.screen ? j.cb16 + (size_t)bf16_rows(k) * 16 * j.screen : nullptr;
+    j.cnB = j.screen ? at<float>(base, o_cnb) : nullptr;
   }
   return c.off;
 }
@@ -273,11 +286,15 @@ km_status begin_stage(Job& j, int stage, hipStream_t s) {
   const void* X = stage == 1 ? j.xs : j.X;
   const int64_t rows = stage == 1 ? j.m : r.n;
   HIP_TRY(stage_reset(j.st, s));
-  HIP_TRY(row_stats(X, dt, rows, r.d, false, j.st, s));
+  // the screen's score offset needs max ||x||^2 of the stage's rows
+  HIP_TRY(row_stats(X, dt, rows, r.d, j.screen != 0, j.st, s));
   HIP_TRY(stage_begin(j.st, r.max_iter[stage - 1], r.tol[stage - 1], rows, j.cnorm, r.k, r.d, 0,
                       s));
+  if (j.screen)
+    HIP_TRY(prep_bf16(j.c64, r.k, r.d, 16 * j.screen, j.st, j.cb16, j.cnB, s, j.cb16lo));
   HIP_TRY(zero_i64(j.slots, (int64_t)kSlots * r.k * (r.d + 1), s));
   j.phase = stage;
+  j.iter_now = 0;
 done:
   return rc;
 }
@@ -312,6 +329,7 @@ class Engine {
     int dtype, dmax, ppt, ktile;
     size_t lds;
     int blocks;
+    int screen;  // K steps of the batched BF16 screen, 0 for the FP32 kernel
   };
 
   explicit Engine(hipStream_t s) : s_(s) {}
@@ -319,7 +337,7 @@ class Engine {
 
   km_status init() {
     km_status rc = KM_OK;
-    const size_t heads = sizeof(BatchHead) * (kMaxShapes + 1);
+    const size_t heads = sizeof(BatchHead) * (kMaxShapes + 2);
     const size_t insts = sizeof(BatchInst) * (size_t)kTableCap * (kMaxShapes + 1);
     const size_t stat = sizeof(BatchStatus) * kTableCap;
     bytes_ = heads + insts + stat;
@@ -336,28 +354,32 @@ class Engine {
   }
 
   // Shape slot for a register tile and LDS center tile (created on first use).
-  int shape_of(int dtype, int dmax, int ppt, int ktile) {
+  int shape_of(int dtype, int dmax, int ppt, int ktile, int screen = 0) {
     for (int i = 0; i < (int)shapes_.size(); ++i)
       if (shapes_[i].dtype == dtype && shapes_[i].dmax == dmax && shapes_[i].ppt == ppt &&
-          shapes_[i].ktile == ktile)
+          shapes_[i].ktile == ktile && shapes_[i].screen == screen)
         return i;
     if ((int)shapes_.size() >= kMaxShapes) return -1;
-    Shape sh{dtype, dmax, ppt, ktile, batch_lds(dmax, ktile), 0};
+    // the screen's LDS holds only the privatised sums
+    Shape sh{dtype, dmax, ppt, ktile, screen ? kSumsLds : batch_lds(dmax, ktile), 0, screen};
     sh.blocks = (int)std::max<int64_t>(
-        1, batch_resident_blocks(dtype, dmax, ppt, sh.lds, device_cus()));
+        1, batch_resident_blocks(dtype, dmax, ppt, sh.lds, device_cus(), screen));
     shapes_.push_back(sh);
     return (int)shapes_.size() - 1;
   }
 
-  // One batched pass for the given problems (each in phase 1, 2 or 3).
-  km_status round(const std::vector<Job*>& act, bool graphs, std::vector<BatchStatus>& st) {
+  // `passes` batched passes for the given problems (each in phase 1, 2 or 3),
+  // then their statuses.  A problem whose stage stops inside the chunk keeps its
+  // done flag, and the kernels of the later passes skip it.
+  km_status round(const std::vector<Job*>& act, bool graphs, int passes,
+                  std::vector<BatchStatus>& st) {
     km_status rc = KM_OK;
     const int na = (int)act.size();
     if (na > kTableCap) return fail(KM_EINVAL, "more than %d active problems", kTableCap);
     const int ns = (int)shapes_.size();
     std::vector<int> cnt(ns, 0);
     std::vector<int64_t> units(ns, 0);
-    int64_t centers = 0;
+    int64_t centers = 0, sunits = 0;
     unsigned mask = 0;
     for (int a = 0; a < na; ++a) {
       Job& j = *act[a];
@@ -370,6 +392,10 @@ class Engine {
       b.dtype = j.rq.dtype == KM_F32 ? 0 : 1;
       b.mode = j.phase == 3 ? 2 : 1;
       b.lds_sums = (size_t)j.rq.k * (j.rq.d + 1) * 8 <= kSumsLds ? 1 : 0;
+      b.cb16 = j.cb16;
+      b.cb16lo = j.cb16lo;
+      b.cnB = j.cnB;
+      b.kd16 = 16 * j.screen;
       b.ktile = j.tv.ktile;
       b.tile_pts = 256LL * shapes_[g].ppt;
       b.unit0 = units[g];
@@ -386,6 +412,13 @@ class Engine {
       b.labels = j.labels;
       b.Jpart = j.jpart;
       b.upart = j.upart;
+      // sums too large for the assignment's LDS: ranges of points x centers
+      b.skc = (int32_t)std::min<int64_t>(b.k, kBatchSumLds / ((size_t)(b.d + 1) * 8));
+      b.sunit0 = sunits;
+      b.sunits = b.mode == 1 && !b.lds_sums
+                     ? (b.n + kBatchSumPts - 1) / kBatchSumPts * ((b.k + b.skc - 1) / b.skc)
+                     : 0;
+      sunits += b.sunits;
       units[g] += b.units;
       centers += b.k;
       h_insts_[(size_t)g * kTableCap + cnt[g]++] = b;
@@ -394,6 +427,7 @@ class Engine {
     }
     for (int g = 0; g < ns; ++g) h_heads_[g] = BatchHead{cnt[g], 0, units[g], 0};
     h_heads_[kMaxShapes] = BatchHead{na, 0, 0, centers};
+    h_heads_[kMaxShapes + 1] = BatchHead{na, 0, sunits, 0};
     // descriptors: only the used prefix of each table travels
     for (int g = 0; g < ns; ++g)
       if (cnt[g])
@@ -402,26 +436,28 @@ class Engine {
     HIP_TRY(hipMemcpyAsync(d_insts_ + (size_t)kMaxShapes * kTableCap,
                            h_insts_ + (size_t)kMaxShapes * kTableCap, sizeof(BatchInst) * na,
                            hipMemcpyHostToDevice, s_));
-    HIP_TRY(hipMemcpyAsync(d_heads_, h_heads_, sizeof(BatchHead) * (kMaxShapes + 1),
+    HIP_TRY(hipMemcpyAsync(d_heads_, h_heads_, sizeof(BatchHead) * (kMaxShapes + 2),
                            hipMemcpyHostToDevice, s_));
     if (graphs) {
       hipGraphExec_t ex = nullptr;
-      rc = graph_for(mask, &ex);
+      rc = graph_for(mask, passes, &ex);
       if (rc != KM_OK) goto done;
       HIP_TRY(hipGraphLaunch(ex, s_));
     } else {
-      rc = launch(mask);
+      for (int p = 0; p < passes && rc == KM_OK; ++p) rc = launch(mask);
       if (rc != KM_OK) goto done;
     }
     HIP_TRY(hipMemcpyAsync(hstat_, d_stat_, sizeof(BatchStatus) * na, hipMemcpyDeviceToHost, s_));
     HIP_TRY(hipStreamSynchronize(s_));
     st.assign(hstat_, hstat_ + na);
-    ++rounds_;
+    rounds_ += passes;
+    ++syncs_;
   done:
     return rc;
   }
 
   int64_t rounds() const { return rounds_; }
+  int64_t syncs() const { return syncs_; }
   hipStream_t stream() const { return s_; }
 
  private:
@@ -430,9 +466,11 @@ class Engine {
     for (int g = 0; g < (int)shapes_.size(); ++g) {
       if (!(mask & (1u << g))) continue;
       const Shape& sh = shapes_[g];
-      BatchShape bs{sh.dtype, sh.dmax, sh.ppt, sh.lds, sh.blocks};
+      BatchShape bs{sh.dtype, sh.dmax, sh.ppt, sh.lds, sh.blocks, sh.screen};
       HIP_TRY(batch_assign(d_heads_ + g, d_insts_ + (size_t)g * kTableCap, bs, s_));
     }
+    HIP_TRY(batch_sums(d_heads_ + kMaxShapes + 1, d_insts_ + (size_t)kMaxShapes * kTableCap,
+                       2 * device_cus(), s_));
     HIP_TRY(batch_finalize(d_heads_ + kMaxShapes, d_insts_ + (size_t)kMaxShapes * kTableCap,
                            kFinalizeBlocks, s_));
     HIP_TRY(batch_status(d_heads_ + kMaxShapes, d_insts_ + (size_t)kMaxShapes * kTableCap, d_stat_,
@@ -441,10 +479,11 @@ class Engine {
     return rc;
   }
 
-  // The launches of a round for a set of shapes, captured once and replayed.
-  km_status graph_for(unsigned mask, hipGraphExec_t* out) {
+  // The launches of `passes` rounds for a set of shapes, captured once and replayed.
+  km_status graph_for(unsigned mask, int passes, hipGraphExec_t* out) {
     km_status rc = KM_OK;
-    auto it = graphs_.find(mask);
+    const uint64_t key = (uint64_t)mask << 8 | (uint64_t)passes;
+    auto it = graphs_.find(key);
     if (it != graphs_.end()) {
       *out = it->second;
       return KM_OK;
@@ -452,7 +491,7 @@ class Engine {
     hipGraph_t g = nullptr;
     hipGraphExec_t ex = nullptr;
     HIP_TRY(hipStreamBeginCapture(s_, hipStreamCaptureModeThreadLocal));
-    rc = launch(mask);
+    for (int p = 0; p < passes && rc == KM_OK; ++p) rc = launch(mask);
     {
       const hipError_t e = hipStreamEndCapture(s_, &g);
       if (rc != KM_OK) goto done;
@@ -462,7 +501,7 @@ class Engine {
       }
     }
     HIP_TRY(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
-    graphs_[mask] = ex;
+    graphs_[key] = ex;
     *out = ex;
   done:
     if (g) (void)hipGraphDestroy(g);
@@ -488,8 +527,8 @@ class Engine {
   BatchInst *d_insts_ = nullptr, *h_insts_ = nullptr;
   BatchStatus* d_stat_ = nullptr;
   std::vector<Shape> shapes_;
-  std::unordered_map<unsigned, hipGraphExec_t> graphs_;
-  int64_t rounds_ = 0;
+  std::unordered_map<uint64_t, hipGraphExec_t> graphs_;
+  int64_t rounds_ = 0, syncs_ = 0;
 };
 
 // Admission of a problem: shape from the autotuner, workspace, the first stage.
@@ -498,9 +537,15 @@ km_status admit(Engine& eng, Job& j, hipStream_t s) {
   const km_request& r = j.rq;
   const int dt = r.dtype == KM_F32 ? 0 : 1;
   j.dmax = batch_dmax(r.d);
-  rc = tuned(dt, j.dmax, r.k, s, &j.tv);
-  if (rc != KM_OK) return rc;
-  j.shape = eng.shape_of(dt, j.dmax, j.tv.ppt, j.tv.ktile);
+  if (j.screen) {
+    // the BF16 screen: 256-point units, no register-tile choice to tune
+    j.tv.ppt = 1;
+    j.tv.ktile = 32;
+  } else {
+    rc = tuned(dt, j.dmax, r.k, s, &j.tv);
+    if (rc != KM_OK) return rc;
+  }
+  j.shape = eng.shape_of(dt, j.dmax, j.tv.ppt, j.tv.ktile, j.screen);
   if (j.shape < 0) return fail(KM_EBUSY, "too many register-tile shapes at once");
   rc = j.mem.get(j.bytes, nullptr, 0, s);
   if (rc != KM_OK) return rc;
@@ -511,6 +556,7 @@ km_status admit(Engine& eng, Job& j, hipStream_t s) {
 // After a round: stage changes and completion.  Returns true when finished.
 bool advance(Job& j, const BatchStatus& b, hipStream_t s) {
   const km_request& r = j.rq;
+  j.iter_now = b.iter;
   if (b.nonfinite) {
     j.status = fail(KM_EINVAL, "X contains NaN or Inf");
     j.err = g_err;
@@ -556,6 +602,18 @@ bool advance(Job& j, const BatchStatus& b, hipStream_t s) {
     return true;
   }
   return false;
+}
+
+// Passes for the next chunk: at most `cap`, and no more than any problem may
+// still need before its stage reaches max_iter (one for a labelling pass), so
+// a problem waits past its stage's end only when tol stops it early.
+int chunk_passes(const std::vector<Job*>& act, int cap) {
+  int r = std::max(1, std::min(cap, kMaxChunk));
+  for (const Job* j : act) {
+    const int rem = j->phase == 3 ? 1 : j->rq.max_iter[j->phase - 1] - j->iter_now;
+    r = std::min(r, std::max(1, rem));
+  }
+  return r;
 }
 
 void fill_result(const Job& j, km_result* out) {
@@ -639,7 +697,8 @@ void km_server::loop() {
     if (!active.empty()) {
       std::vector<Job*> act;
       for (auto& jp : active) act.push_back(jp.get());
-      const km_status rc = eng->round(act, cfg.use_graphs != 0, stat);
+      const int passes = chunk_passes(act, cfg.passes_per_sync);
+      const km_status rc = eng->round(act, cfg.use_graphs != 0, passes, stat);
       std::vector<std::unique_ptr<Job>> keep;
       for (size_t a = 0; a < active.size(); ++a) {
         bool fin;
@@ -673,6 +732,7 @@ void km_server::loop() {
       ctr.bytes_in_use = in_use;
       ctr.peak_bytes = std::max(ctr.peak_bytes, in_use);
       ctr.rounds = eng->rounds();
+      ctr.syncs = eng->syncs();
     }
     if (!done_now.empty()) cv_done.notify_all();
   }
@@ -734,6 +794,7 @@ km_status fit_batch_on(const km_request* reqs, int32_t count, km_result* results
       continue;
     }
     j.m = subset_size(j.rq.n, j.rq.k, j.rq.subset_frac);
+    j.screen = batch_screen_ks(j.rq.dtype == KM_F32 ? 0 : 1, j.rq.d, j.rq.k);
     j.bytes = job_layout(j, nullptr);
     const km_status ra = admit(eng, j, s);
     if (ra != KM_OK) {
@@ -749,7 +810,7 @@ km_status fit_batch_on(const km_request* reqs, int32_t count, km_result* results
   std::vector<Job*> run, waiting;
   for (Job* j : act) (run.size() < (size_t)kTableCap ? run : waiting).push_back(j);
   while (!run.empty()) {
-    rc = eng.round(run, true, stat);
+    rc = eng.round(run, true, chunk_passes(run, 8), stat);
     if (rc != KM_OK) break;
     std::vector<Job*> keep;
     for (size_t a = 0; a < run.size(); ++a)
@@ -803,6 +864,8 @@ km_status km_server_create(const km_server_cfg* cfg, km_server** out) {
   if (srv->cfg.max_active <= 0) srv->cfg.max_active = 4096;
   srv->cfg.max_active = std::min(srv->cfg.max_active, kTableCap);
   if (srv->cfg.max_pending <= 0) srv->cfg.max_pending = 1 << 20;
+  if (srv->cfg.passes_per_sync <= 0) srv->cfg.passes_per_sync = 4;
+  srv->cfg.passes_per_sync = std::min(srv->cfg.passes_per_sync, kMaxChunk);
   if (hipGetDevice(&srv->device) != hipSuccess) return fail(KM_EDEVICE, "no HIP device");
   size_t fr = 0, tot = 0;
   if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(KM_EDEVICE, "hipMemGetInfo failed");
@@ -829,6 +892,7 @@ km_status km_server_submit(km_server* srv, const km_request* req, uint64_t* tick
   if (!valid_request(j->rq, true)) return KM_EINVAL;
   j->copy_x = true;
   j->m = subset_size(j->rq.n, j->rq.k, j->rq.subset_frac);
+  j->screen = batch_screen_ks(j->rq.dtype == KM_F32 ? 0 : 1, j->rq.d, j->rq.k);
   j->bytes = job_layout(*j, nullptr);
   j->t_submit = now_s();
   std::lock_guard<std::mutex> lk(srv->mu);

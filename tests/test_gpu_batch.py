@@ -129,6 +129,47 @@ def test_server_result_same_alone_and_in_mix():
     _check_against_oracle(Xh, C1, L1, info1, k, f, seed, mi, tl, "served")
 
 
+@pytest.mark.parametrize("d,k,comps", [(128, 64, 8), (32, 200, 20), (100, 40, 4)])
+def test_fit_batch_bf16_screen_tight_clusters_far_out(d, k, comps):
+    """Tight components far from the origin with several centers each: many
+    points have three or more centers inside the screen's error band, so the
+    candidate lists (and, beyond them, the FP64 check over all centers) decide."""
+    spec = synth.MixtureSpec(d, comps, "uniform", -50.0, 50.0, sigma_lo=0.5, sigma_hi=0.5,
+                             weights="dirichlet1")
+    Xh = synth.generate(spec, 4321 + d, 12_000, "bf16")
+    X = torch.from_numpy(Xh.view(np.int16)).cuda().view(torch.bfloat16)
+    mi, tl = (5, 8), (0.0, 0.0)
+    (C, L, info), = km.kmeans_fit_batch([(X, k, 0.05, 7, mi, tl)])
+    _check_against_oracle(Xh, C, L, info, k, 0.05, 7, mi, tl, f"tight {d} {k}")
+
+
+def test_server_pass_chunks_same_results():
+    """Chunks of passes between host synchronisations change nothing but the
+    number of synchronisations: problems that stop early (tol) inside a chunk are
+    skipped by the device until it ends."""
+    rng = np.random.default_rng(11)
+    probs = [(_problem(int(rng.integers(2_000, 30_000)), int(d), int(rng.integers(4, 40)), 700 + i,
+                       "f32" if d < 32 else "bf16"))
+             for i, d in enumerate(rng.choice([3, 8, 16, 64, 128], size=16))]
+    out = {}
+    for pps in (1, 8):
+        with km.Server(passes_per_sync=pps) as srv:
+            ts = [_serve_one(srv, Xh, min(24, len(Xh) // 50), 0.05, i, (20, 30), (1e-3, 1e-4))
+                  for i, Xh in enumerate(probs)]
+            out[pps] = [srv.wait(t, timeout=120) for t in ts]
+            out[pps, "st"] = srv.stats()
+    for i in range(len(probs)):
+        C1, L1, i1 = out[1][i]
+        C8, L8, i8 = out[8][i]
+        assert torch.equal(C1, C8) and torch.equal(L1, L8), i
+        assert i1["iters"] == i8["iters"] and i1["J"] == i8["J"], i
+    assert out[8, "st"]["syncs"] < out[1, "st"]["syncs"]
+    assert out[1, "st"]["syncs"] == out[1, "st"]["rounds"]
+    Xh = probs[0]
+    _check_against_oracle(Xh, *out[8][0], min(24, len(Xh) // 50), 0.05, 0, (20, 30), (1e-3, 1e-4),
+                          "chunked")
+
+
 def test_server_admission_respects_budget():
     probs = [(_problem(20_000, 8, 8, 900 + i, "f32"), 8) for i in range(6)]
     with km.Server() as probe:
@@ -200,3 +241,40 @@ def test_server_destroy_with_jobs_in_flight_and_blocked_waiter():
     Xh = _problem(2_000, 4, 5, 11, "f32")
     _check_against_oracle(Xh, *km.kmeans_fit_batch([(to_device(Xh), 5, 0.1, 1, 20, 1e-4)])[0],
                           5, 0.1, 1, (20, 20), (1e-4, 1e-4), "after destroy")
+
+
+def test_server_bf16_128d_target_same_alone_and_in_mix():
+    """A 128-D BF16 request (the batched BF16 MFMA screen) gives the same bits
+    alone and among other requests of every shape, and matches the oracle."""
+    target = (_problem(40_000, 128, 48, 91, "bf16"), 48, 0.02, 6, (20, 20), (1e-4, 1e-4))
+    Xh, k, f, seed, mi, tl = target
+    with km.Server() as srv:
+        t = _serve_one(srv, Xh, k, f, seed, mi, tl)
+        C0, L0, info0 = srv.wait(t, timeout=120)
+    rng = np.random.default_rng(8)
+    others = [(_problem(int(rng.integers(500, 30000)), int(d), int(rng.integers(3, 40)),
+                        700 + i, "f32" if d < 32 else "bf16"))
+              for i, d in enumerate(rng.choice([2, 8, 32, 64, 128], size=20))]
+    with km.Server() as srv:
+        tickets = [_serve_one(srv, Xo, min(32, len(Xo) // 10), 0.1, i, (10, 10), (1e-4, 1e-4))
+                   for i, Xo in enumerate(others[:10])]
+        t = _serve_one(srv, Xh, k, f, seed, mi, tl)
+        tickets += [_serve_one(srv, Xo, min(32, len(Xo) // 10), 0.1, 10 + i, (10, 10),
+                               (1e-4, 1e-4)) for i, Xo in enumerate(others[10:])]
+        C1, L1, info1 = srv.wait(t, timeout=120)
+        for tt in tickets:
+            srv.wait(tt, timeout=120)
+    assert torch.equal(C0, C1) and torch.equal(L0, L1)
+    assert info0["J"] == info1["J"] and info0["iters"] == info1["iters"]
+    _check_against_oracle(Xh, C1, L1, info1, k, f, seed, mi, tl, "served 128-D BF16")
+
+
+@pytest.mark.parametrize("d,k", [(32, 7), (64, 33), (128, 256), (100, 65), (24, 3)])
+def test_fit_batch_bf16_screen_shapes(d, k):
+    """The batched BF16 screen over its shapes: 2, 4 or 8 K steps, partial last
+    center tile, k up to 256, d not a multiple of 16, ragged last unit."""
+    n = 9_001
+    Xh = _problem(n, d, max(2, k // 2), 40 + d + k, "bf16")
+    out = km.kmeans_fit_batch([(to_device(Xh), k, 0.2, 3, (8, 8), (1e-5, 1e-5))])
+    C, L, info = out[0]
+    _check_against_oracle(Xh, C, L, info, k, 0.2, 3, (8, 8), (1e-5, 1e-5), f"d={d} k={k}")
