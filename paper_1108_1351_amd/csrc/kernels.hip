@@ -810,10 +810,11 @@ __device__ __forceinline__ void assign_tile(
       double D = 0.0;
 #pragma unroll
       for (int t = 0; t < DMAX; ++t) {
-        if (t < d) {
-          const double diff = (double)x[p][t] - cl[t];
-          D = D + diff * diff;
-        }
+        // a clamped load and a zero term past d: no branch per element, so the
+        // loads of the row are in flight together
+        const double cv = cl[t < d ? t : 0];
+        const double diff = t < d ? (double)x[p][t] - cv : 0.0;
+        D = D + diff * diff;
       }
       Jacc += D;
     }
@@ -1381,10 +1382,9 @@ __device__ __forceinline__ int64_t mfma_fp64_check(bool unc, const float (&x)[H]
       double D = 0.0;
 #pragma unroll
       for (int t = 0; t < 2 * H; ++t) {
-        if (t < d) {
-          const double diff = (double)xv[t] - cj[t];
-          D = D + diff * diff;
-        }
+        const double cv = cj[t < d ? t : 0];
+        const double diff = t < d ? (double)xv[t] - cv : 0.0;
+        D = D + diff * diff;
       }
       if (D < bD) { bD = D; bj = j; }
     }
@@ -1646,10 +1646,10 @@ __device__ __forceinline__ int rerank(const T* __restrict__ xr, int d, int h, bo
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int t = 16 * s + 8 * h + e;
-        if (t < d) {
-          const float diff = widen<T>(xr[t]) - cj[t];
-          part = __builtin_fmaf(diff, diff, part);
-        }
+        const int tc = t < d ? t : 0;
+        const float cv = cj[tc], xv = widen<T>(xr[tc]);
+        const float diff = t < d ? xv - cv : 0.f;
+        part = __builtin_fmaf(diff, diff, part);
       }
     const float D = part + __shfl_xor(part, 32);
     if (active && q < nc) {
@@ -1679,10 +1679,10 @@ __device__ __forceinline__ int rerank(const T* __restrict__ xr, int d, int h, bo
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int t = 16 * s + 8 * h + e;
-          if (t < d) {
-            const double diff = (double)widen<T>(xr[t]) - cj[t];
-            part = __builtin_fma(diff, diff, part);
-          }
+          const int tc = t < d ? t : 0;
+          const double cv = cj[tc], xv = (double)widen<T>(xr[tc]);
+          const double diff = t < d ? xv - cv : 0.0;
+          part = __builtin_fma(diff, diff, part);
         }
       const double D = part + __shfl_xor(part, 32);
       if (need && q < nc && (D < b64 || (D == b64 && j < b64j))) {
@@ -3164,7 +3164,8 @@ __device__ void finalize_center(
     const double* __restrict__ Jpart, const long long* __restrict__ upart, int64_t nb,
     double* __restrict__ J_hist, double* __restrict__ shift_hist, bool mark_labelled = false,
     bool biased = false, double* __restrict__ trace_c = nullptr,
-    long long* __restrict__ trace_n = nullptr, uint16_t* __restrict__ cb16lo = nullptr) {
+    long long* __restrict__ trace_n = nullptr, uint16_t* __restrict__ cb16lo = nullptr,
+    int nslots = kSlots) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t C = (int64_t)k * (d + 1);
   // this pass's index in the stage (the last block of the pass advances it
@@ -3179,7 +3180,8 @@ __device__ void finalize_center(
   __shared__ int last;
   if (wv == 0) {
     long long v = 0;
-    if (lane < kSlots) {
+    if (lane < kSlots) scnt[lane] = 0;
+    if (lane < nslots) {
       v = col[(int64_t)lane * C + d];
       col[(int64_t)lane * C + d] = 0;
       scnt[lane] = v;
@@ -3195,7 +3197,7 @@ __device__ void finalize_center(
   for (int t0 = 0; t0 < d; t0 += 8) {
     const int t = t0 + c;
     long long sv = 0;
-    if (t < d) {
+    if (t < d && r < nslots) {
       sv = col[(int64_t)r * C + t];
       col[(int64_t)r * C + t] = 0;
       // biased sums: every point added kSumBias + q (mod 2^64)
@@ -3462,14 +3464,26 @@ __global__ __launch_bounds__(256) void k_sum_J(PassState* __restrict__ st,
 // which: 0 assignment units, 1 finalize entries, 2 cluster-sum units (an
 // instance without sum units shares its first entry with the next one and is
 // never the last such).
+// The 64 lanes of a wave probe 64 evenly spaced instances at once, so a
+// search takes two dependent loads for up to 4096 instances and three for
+// 8192 (every lane of the wave must call it with the same u).
 __device__ __forceinline__ int batch_find(const BatchInst* __restrict__ bi, int ninst, int64_t u,
                                           int which) {
-  int lo = 0, hi = ninst;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    const int64_t s0 = which == 1 ? bi[mid].center0 : which == 2 ? bi[mid].sunit0 : bi[mid].unit0;
-    if (s0 <= u) lo = mid;
-    else hi = mid;
+  const int lane = threadIdx.x & 63;
+  int lo = 0, span = ninst;  // the answer lies in [lo, lo + span); bi[lo] starts at or before u
+  while (span > 1) {
+    const int step = (span + 63) >> 6;
+    const int idx = lo + lane * step;
+    bool ok = false;
+    if (lane * step < span) {
+      const BatchInst& c = bi[idx];
+      const int64_t s0 = which == 1 ? c.center0 : which == 2 ? c.sunit0 : c.unit0;
+      ok = s0 <= u;
+    }
+    const unsigned long long m = __ballot(ok);
+    const int L = 63 - __clzll((long long)m);
+    lo += L * step;
+    span = min(step, span - L * step);
   }
   return lo;
 }
@@ -3497,7 +3511,7 @@ __global__ __launch_bounds__(256) void k_batch_assign(const BatchHead* __restric
     float* cnl = w + (size_t)ktile * DMAX;
     unsigned long long* S = nullptr;
     const bool lds = b.mode == 1 && b.lds_sums;
-    const int slot = (int)(tile & (kSlots - 1));
+    const int slot = (int)(tile & (b.nslots - 1));
     unsigned long long* row =
         reinterpret_cast<unsigned long long*>(b.slots + (int64_t)slot * k * (d + 1));
     if (lds) {
@@ -3538,17 +3552,20 @@ __global__ __launch_bounds__(256) void k_batch_assign(const BatchHead* __restric
 // band of two scores (the centers' exact rounding error norm dcn, the FP32
 // accumulation) certifies the best; when two or three keys lie inside it and
 // the fourth does not, FP64 distances decide among them; otherwise the wave's
-// FP64 check over all centers decides.  Then J (FP64 direct form), the label
-// and (when they fit in LDS) the exact cluster sums, as in the FP32 batched
-// kernel; larger sums are added by k_batch_sums from the labels.
+// FP64 check over all centers decides.  Then J (FP64 direct form) and the
+// label; k_batch_sums adds the exact cluster sums from the labels.
 template <int KS>
-__global__ __launch_bounds__(256, 2) void k_batch_screen(const BatchHead* __restrict__ hd,
+__global__ __launch_bounds__(256, 3) void k_batch_screen(const BatchHead* __restrict__ hd,
                                                       const BatchInst* __restrict__ bi) {
   constexpr int KD = KS * 16;
   constexpr int C8 = KD / 8;     // 16-byte chunks per center row of the copy
   constexpr int BG = 8;          // index bits of a key (k <= 256)
   constexpr int GM = (1 << BG) - 1;
-  extern __shared__ __align__(16) unsigned char smem[];
+  // tiles of the copy (hi, lo: C8 * 32 chunks of 16 bytes each) and their
+  // biases, double-buffered
+  constexpr int TE = C8 * 32 * 8;  // BF16 elements of one part of a tile
+  __shared__ __align__(16) uint16_t tl[2][2][TE];
+  __shared__ __align__(16) float tb[2][32];
   const int lane = threadIdx.x & 63, h = lane >> 5, pc = lane & 31;
   const int wave = threadIdx.x >> 6;
   const int ninst = hd->ninst;
@@ -3565,18 +3582,6 @@ __global__ __launch_bounds__(256, 2) void k_batch_screen(const BatchHead* __rest
     const uint16_t* cbl = b.cb16lo;
     const float* cnB = b.cnB;
     const int64_t n = b.n;
-    unsigned long long* S = nullptr;
-    const bool lds = b.mode == 1 && b.lds_sums;
-    const int slot = (int)(tile & (kSlots - 1));
-    unsigned long long* row =
-        reinterpret_cast<unsigned long long*>(b.slots + (int64_t)slot * k * (d + 1));
-    if (lds) {
-      S = reinterpret_cast<unsigned long long*>(smem);
-      for (int e = threadIdx.x; e < k * (d + 1); e += 256) S[e] = 0ull;
-      __syncthreads();
-    } else if (b.mode == 1 && b.sunits == 0) {
-      S = row;  // otherwise k_batch_sums adds them after the labels are written
-    }
     // the wave's 64 points: tile A (points 0..31) and tile B (32..63) of its part
     const int64_t p0 = tile * 256 + (int64_t)wave * 64;
     const int64_t iA = p0 + pc, iB = p0 + 32 + pc;
@@ -3607,39 +3612,95 @@ __global__ __launch_bounds__(256, 2) void k_batch_screen(const BatchHead* __rest
         insert(m, (__float_as_int(acc[r]) & ~GM) | j);
       }
     };
-    // A operands (hi and lo parts) and C input of center tile t (rows 32t ..
-    // 32t + 31 of the copy)
-    auto load_a = [&](int t, v8bf (&a)[KS], v8bf (&al)[KS], v16f& bias) {
+    // Per point: ||x||^2 (BF16 data: the MFMA sees x exactly), the error bound
+    // e1 of one score, and the offset that the C input adds to ||c||^2 + B so
+    // that a score is ||x - c||^2 + margin: its magnitude is that of the
+    // distance, so the keys lose little to the index bits, and it stays >= 0.
+    // e1: the centers' rounding (||x|| dcn), the FP32 accumulation from the C
+    // input over 2 KD products (magnitudes up to ||c||^2 + ||x||^2 and
+    // 2 ||x|| ||c||), and the roundings of ||c||^2 + B and of the offset.
+    float e1v[2], offv[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const v8bf* x = p == 0 ? xA : xB;
+      float s2 = 0.f;
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const int64_t o = ((int64_t)(t * C8 + 2 * s + h) * 32 + pc) * 8;
-        a[s] = *reinterpret_cast<const v8bf*>(cb + o);
-        al[s] = *reinterpret_cast<const v8bf*>(cbl + o);
-      }
+        const uint4 w = __builtin_bit_cast(uint4, x[s]);
+        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const float4 v = *reinterpret_cast<const float4*>(cnB + 32 * t + 8 * g + 4 * h);
-        bias[4 * g] = v.x; bias[4 * g + 1] = v.y; bias[4 * g + 2] = v.z; bias[4 * g + 3] = v.w;
+        for (int q = 0; q < 4; ++q) {
+          const bf16x2 v = __builtin_bit_cast(bf16x2, w4[q]);
+          s2 = __builtin_amdgcn_fdot2_f32_bf16(v, v, s2, false);
+        }
+      }
+      const float xn2 = s2 + __shfl_xor(s2, 32);
+      const float xn = sqrtf(xn2) * 1.01f;
+      const float e1 = ea * (cmax * cmax + xn2 * 1.01f + 2.f * xn * cmax) + xn * dcn +
+                       3.f * 0x1p-23f * (B + cmax * cmax + xn2);
+      // ||x||^2 above is an FP32 sum of KD products
+      const float margin = e1 + (float)(KD + 8) * 0x1p-23f * 1.01f * xn2 + 1e-30f;
+      e1v[p] = e1 * 1.001f;
+      // ||c||^2 - 2 x.c = ||x - c||^2 - ||x||^2: the offset adds ||x||^2 back
+      offv[p] = margin + xn2 - B;
+    }
+    // Tile t of the copy into LDS buffer q with LDS-direct loads (a tile's
+    // part is one contiguous range of the tiled copy, 1 KB per wave
+    // instruction); the four waves share it.
+    auto issue_tile = [&](int t, int q) {
+      static_assert(TE % 512 == 0, "a tile's part is whole 1 KB pieces");
+#pragma unroll
+      for (int i = wave; i < TE / 512; i += 4) {
+        __builtin_amdgcn_global_load_lds(
+            static_cast<const void*>(cb + (int64_t)t * TE + i * 512 + lane * 8),
+            static_cast<void*>(&tl[q][0][i * 512]), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(
+            static_cast<const void*>(cbl + (int64_t)t * TE + i * 512 + lane * 8),
+            static_cast<void*>(&tl[q][1][i * 512]), 16, 0, 0);
+      }
+      if (wave == 3 && lane < 32)
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(cnB + 32 * t + lane),
+                                         static_cast<void*>(&tb[q][0]), 4, 0, 0);
+    };
+    // One sweep over the center tiles (every wave of the block takes part: the
+    // tiles pass through LDS): the scores of the wave's two point tiles, handed
+    // to `use(acc, t, p)` tile by tile.
+    auto sweep = [&](auto&& use) {
+      // the buffers may still be read by an earlier sweep's last tile
+      __syncthreads();
+      issue_tile(0, 0);
+      for (int t = 0; t < nct; ++t) {
+        const int q = t & 1;
+        // tile t is in LDS, and every wave is done with tile t - 1
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t + 1 < nct) issue_tile(t + 1, q ^ 1);
+        v16f accA, accB;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const float4 v = *reinterpret_cast<const float4*>(&tb[q][8 * g + 4 * h]);
+          const float cv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            accA[4 * g + e] = cv[e] + offv[0];
+            accB[4 * g + e] = cv[e] + offv[1];
+          }
+        }
+#pragma unroll
+        for (int part = 0; part < 2; ++part)
+#pragma unroll
+          for (int s = 0; s < KS; ++s) {
+            const v8bf a =
+                *reinterpret_cast<const v8bf*>(&tl[q][part][((2 * s + h) * 32 + pc) * 8]);
+            accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xA[s], accA, 0, 0, 0);
+            accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xB[s], accB, 0, 0, 0);
+          }
+        use(accA, t, 0);
+        use(accB, t, 1);
       }
     };
-    v8bf a[KS], al[KS];
-    v16f bias;
-    for (int t = 0; t < nct; ++t) {
-      load_a(t, a, al, bias);
-      v16f accA = bias, accB = bias;
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xA[s], accA, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xB[s], accB, 0, 0, 0);
-      }
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xA[s], accA, 0, 0, 0);
-        accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xB[s], accB, 0, 0, 0);
-      }
-      rank(accA, t, ga);
-      rank(accB, t, gb);
-    }
+    sweep([&](const v16f& acc, int t, int p) { rank(acc, t, p == 0 ? ga : gb); });
     // merge the lane halves: both lanes of a point get its best four keys
     auto merge_halves = [&](int (&m)[4]) {
       int o[4];
@@ -3670,26 +3731,11 @@ __global__ __launch_bounds__(256, 2) void k_batch_screen(const BatchHead* __rest
     float thr[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const v8bf* x = p == 0 ? xA : xB;
       const bool valid = p == 0 ? vA : vB;
       int g[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) g[q] = p == 0 ? ga[q] : gb[q];
-      // ||x||^2 of the point (BF16 data: the MFMA sees x exactly)
-      float s2 = 0.f;
-      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-#pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const uint4 w = __builtin_bit_cast(uint4, x[s]);
-        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const bf16x2 v = __builtin_bit_cast(bf16x2, w4[q]);
-          s2 = __builtin_amdgcn_fdot2_f32_bf16(v, v, s2, false);
-        }
-      }
-      const float xn = sqrtf(s2 + __shfl_xor(s2, 32)) * 1.01f;
-      const float E2 = 2.f * xn * dcn + 2.f * ea * (cmax * cmax + B + 2.f * xn * cmax);
+      const float E2 = 2.f * e1v[p];
       auto apart = [&](float lo, float hi) {
         return (hi - lo) > E2 + delta * (fabsf(hi) + fabsf(lo));
       };
@@ -3711,92 +3757,73 @@ __global__ __launch_bounds__(256, 2) void k_batch_screen(const BatchHead* __rest
       // E2 above the smallest score; the key of that score is within delta
       thr[p] = (v1 + E2 + delta * (2.f * fabsf(v1) + E2)) * 1.0001f;
     }
-    if (__ballot(fullv[0] || fullv[1])) {
+    // the second sweep runs when any wave of the block has a full point
+    if (__syncthreads_or(fullv[0] || fullv[1])) {
       if (h == 0) ccnt[wave][0][pc] = ccnt[wave][1][pc] = 0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      v8bf a[KS], al[KS];
-      v16f bias;
-      for (int t = 0; t < nct; ++t) {
-        load_a(t, a, al, bias);
-        v16f accA = bias, accB = bias;
+      sweep([&](const v16f& acc, int t, int p) {
+        if (!fullv[p]) return;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xA[s], accA, 0, 0, 0);
-          accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[s], xB[s], accB, 0, 0, 0);
-        }
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          accA = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xA[s], accA, 0, 0, 0);
-          accB = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s], xB[s], accB, 0, 0, 0);
-        }
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-          if (!fullv[p]) continue;
-          const v16f& acc = p == 0 ? accA : accB;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int j = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
-            if (j < k && acc[r] <= thr[p]) {
-              const int c = atomicAdd(&ccnt[wave][p][pc], 1);
-              if (c < kBatchCands) cand[wave][p][pc][c] = (uint8_t)j;
-            }
+        for (int r = 0; r < 16; ++r) {
+          const int j = 32 * t + 8 * (r >> 2) + 4 * h + (r & 3);
+          if (j < k && acc[r] <= thr[p]) {
+            const int c = atomicAdd(&ccnt[wave][p][pc], 1);
+            if (c < kBatchCands) cand[wave][p][pc][c] = (uint8_t)j;
           }
         }
-      }
+      });
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       __builtin_amdgcn_wave_barrier();
     }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const v8bf* x = p == 0 ? xA : xB;
       const int64_t i = p == 0 ? iA : iB;
       const bool valid = p == 0 ? vA : vB;
       const bool pair = pairv[p];
       const int nc = ncv[p];
       int bi1 = best[p];
       const int* gq = p == 0 ? ga : gb;
-      // FP64 direct form over the lane half's dims, then both halves'
+      // FP64 direct form over the lane half's dims, then both halves'.  The
+      // row is read again (it is in cache), eight dims at a time, so that the
+      // loop need not be unrolled over registers held for the whole tail.
       auto dist64 = [&](int j) {
         const double* cj = b.c64 + (int64_t)j * d;
+        const uint16_t* xr = X + (valid ? i : 0) * d;
         double part = 0.0;
-#pragma unroll
+#pragma unroll 2
         for (int s = 0; s < KS; ++s) {
-          const uint4 w = __builtin_bit_cast(uint4, x[s]);
+          const int t0 = 16 * s + 8 * h;
+          const uint4 w = __builtin_bit_cast(uint4, load8_bf16<uint16_t>(xr, t0, d, true));
           const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+          double cv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) cv[q] = cj[t0 + q < d ? t0 + q : 0];
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
-            const int t = 16 * s + 8 * h + q;
-            if (t < d) {
-              const float xv = (q & 1) ? bf16_hi(w4[q >> 1]) : bf16_lo(w4[q >> 1]);
-              const double e = (double)xv - cj[t];
-              part = __builtin_fma(e, e, part);
-            }
+            const float xv = (q & 1) ? bf16_hi(w4[q >> 1]) : bf16_lo(w4[q >> 1]);
+            const double e = t0 + q < d ? (double)xv - cv[q] : 0.0;
+            part = __builtin_fma(e, e, part);
           }
         }
         return part + __shfl_xor(part, 32);
       };
-      if (__ballot(pair)) {
-        // FP64 distances of the candidates (lowest index on equal values)
-        double bd = dist64(bi1);
-#pragma unroll
-        for (int q = 1; q < 3; ++q) {
-          const bool use = pair && q < nc;
-          if (__ballot(use)) {
-            const int jq = use ? (gq[q] & GM) : bi1;
-            const double dq = dist64(jq);
-            if (use && (dq < bd || (dq == bd && jq < bi1))) {
-              bd = dq;
-              bi1 = jq;
-            }
-          }
-        }
-        pcnt += __popcll(__ballot(pair && h == 0));
-      }
+      // Candidates of pair and full points go into the point's list (a full
+      // point's list was filled by the second sweep); FP64 decides among them
+      // (lowest index on equal values).
       const bool full = fullv[p];
-      if (__ballot(full)) {
-        const int cnt = full ? ccnt[wave][p][pc] : 0;
-        const bool listed = full && cnt >= 1 && cnt <= kBatchCands;
+      if (__ballot(pair || full)) {
+        if (pair && h == 0) {
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            if (q < nc) cand[wave][p][pc][q] = (uint8_t)(gq[q] & GM);
+          ccnt[wave][p][pc] = nc;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cnt = (pair || full) ? ccnt[wave][p][pc] : 0;
+        const bool listed = (pair || full) && cnt >= 1 && cnt <= kBatchCands;
         int qn = listed ? cnt : 0;
         for (int o = 32; o > 0; o >>= 1) qn = max(qn, __shfl_xor(qn, o));
         double bd = INFINITY;
@@ -3825,33 +3852,6 @@ __global__ __launch_bounds__(256, 2) void k_batch_screen(const BatchHead* __rest
       if (valid && h == 0) {
         Jacc += D;
         if (b.labels) b.labels[i] = bi1;
-      }
-      if (valid && S) {
-        // exact sums: rint(x 2^F) of the lane half's dims; the count from half 0
-        unsigned long long* Sr = S + (int64_t)bi1 * (d + 1);
-        const float sc = st->scale;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const uint4 w = __builtin_bit_cast(uint4, x[s]);
-          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int t = 16 * s + 8 * h + q;
-            if (t < d) {
-              const float xv = (q & 1) ? bf16_hi(w4[q >> 1]) : bf16_lo(w4[q >> 1]);
-              const long long qv = (long long)__float2int_rn(xv * sc);
-              atomicAdd(&Sr[t], (unsigned long long)qv);
-            }
-          }
-        }
-        if (h == 0) atomicAdd(&Sr[d], 1ull);
-      }
-    }
-    if (lds) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < k * (d + 1); e += 256) {
-        const unsigned long long v = S[e];
-        if (v) atomicAdd(&row[e], v);
       }
     }
     block_sum_J(Jacc, ucnt, pcnt, b.Jpart, b.upart, tile);
@@ -3971,7 +3971,7 @@ __global__ __launch_bounds__(256) void k_batch_sums(const BatchHead* __restrict_
     }
     __syncthreads();
     unsigned long long* row = reinterpret_cast<unsigned long long*>(
-        b.slots + (int64_t)(pb & (kSlots - 1)) * k * w + (int64_t)c0 * w);
+        b.slots + (int64_t)(pb & (b.nslots - 1)) * k * w + (int64_t)c0 * w);
     for (int e = threadIdx.x; e < cn * w; e += 256) {
       const unsigned long long v = S[e];
       if (v) atomicAdd(&row[e], v);
@@ -3993,7 +3993,7 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const BatchHead* __restr
     finalize_center((int)(c - b.center0), b.slots, nullptr, b.k, b.d, b.st, b.mode == 1 ? 1 : 0,
                     b.c64, b.cw, b.cn, b.cnorm, b.shiftj, b.emptyj, nullptr, nullptr, b.cb16,
                     b.cnB, b.kd16, b.Jpart, b.upart, b.units, b.J_hist, b.shift_hist,
-                    b.mode == 2, false, nullptr, nullptr, b.cb16lo);
+                    b.mode == 2, false, nullptr, nullptr, b.cb16lo, b.nslots);
   }
 }
 

@@ -105,6 +105,9 @@ struct BatchInst {
   // kBatchSumPts points x skc centers), 0 when the assignment adds the sums
   int32_t skc;
   int64_t sunit0, sunits;
+  // slot rows the pass adds into (a power of two <= kSlots; the finalize reads
+  // only these)
+  int32_t nslots;
 };
 struct BatchHead {
   int32_t ninst;

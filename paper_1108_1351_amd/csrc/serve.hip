@@ -107,6 +107,7 @@ km_status tune(int dtype, int dmax, int kb, hipStream_t s, TuneVal* out) {
       bb.dtype = dtype;
       bb.mode = 2;
       bb.lds_sums = 0;
+      bb.nslots = 1;
       bb.ktile = kt;
       bb.unit0 = 0;
       bb.units = hh.units;
@@ -360,8 +361,8 @@ class Engine {
           shapes_[i].ktile == ktile && shapes_[i].screen == screen)
         return i;
     if ((int)shapes_.size() >= kMaxShapes) return -1;
-    // the screen's LDS holds only the privatised sums
-    Shape sh{dtype, dmax, ppt, ktile, screen ? kSumsLds : batch_lds(dmax, ktile), 0, screen};
+    // the screen's LDS is static (center tiles, candidate lists)
+    Shape sh{dtype, dmax, ppt, ktile, screen ? 0 : batch_lds(dmax, ktile), 0, screen};
     sh.blocks = (int)std::max<int64_t>(
         1, batch_resident_blocks(dtype, dmax, ppt, sh.lds, device_cus(), screen));
     shapes_.push_back(sh);
@@ -391,7 +392,9 @@ class Engine {
       b.k = j.rq.k;
       b.dtype = j.rq.dtype == KM_F32 ? 0 : 1;
       b.mode = j.phase == 3 ? 2 : 1;
-      b.lds_sums = (size_t)j.rq.k * (j.rq.d + 1) * 8 <= kSumsLds ? 1 : 0;
+      // the BF16 screen keeps its LDS for the center tiles: its sums always
+      // go through k_batch_sums
+      b.lds_sums = !j.screen && (size_t)j.rq.k * (j.rq.d + 1) * 8 <= kSumsLds ? 1 : 0;
       b.cb16 = j.cb16;
       b.cb16lo = j.cb16lo;
       b.cnB = j.cnB;
@@ -419,6 +422,13 @@ class Engine {
                      ? (b.n + kBatchSumPts - 1) / kBatchSumPts * ((b.k + b.skc - 1) / b.skc)
                      : 0;
       sunits += b.sunits;
+      {
+        // one slot row per writer (tile flushes or point ranges), at most kSlots
+        const int64_t writers = b.sunits ? (b.n + kBatchSumPts - 1) / kBatchSumPts : b.units;
+        int ns = 1;
+        while (ns < kSlots && ns < writers) ns <<= 1;
+        b.nslots = ns;
+      }
       units[g] += b.units;
       centers += b.k;
       h_insts_[(size_t)g * kTableCap + cnt[g]++] = b;
