@@ -2571,7 +2571,7 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
     // Software pipeline over the 32-center tiles: while the MFMAs of tile t
     // accumulate into one set of registers, the key updates of tile t-1 read
     // the other set, and the LDS reads of later steps are in flight (a ring of
-    // four A operands two steps ahead, and the next tile's bias).  accP holds
+    // four A operands three steps ahead, and the next tile's bias).  accP holds
     // the pending tile (index ctP); at the start of a batch it holds scores of
     // 1e30, which never displace a real key (see the merge below).
     v16f accA[PT], accP[PT];
@@ -2615,7 +2615,7 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int i = t * KS + s;
-        if (i + 2 < NSTEP) ring[(i + 2) & 3] = lds_a(cbuf, i + 2);
+        if (i + 3 < NSTEP) ring[(i + 3) & 3] = lds_a(cbuf, i + 3);
 #pragma unroll
         for (int p = 0; p < PT; ++p) {
           out[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ring[i & 3], x[p][s],
@@ -2642,6 +2642,7 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
       lds_bias(bbuf, 0, bias);
       ring[0] = lds_a(cbuf, 0);
       ring[1] = lds_a(cbuf, 1);
+      ring[2] = lds_a(cbuf, 2);
       const int ct0 = gs * NT;
       tile(0, cbuf, bbuf, ring, bias, accA, accP, ctP);
       tile(1, cbuf, bbuf, ring, bias, accP, accA, ct0);
