@@ -2440,7 +2440,7 @@ __global__ __launch_bounds__(256, (KD == 16 && FULL) ? 4 : 3) void k_fused_pair(
 // apart by more than the error band; re-ranked in FP32 (then FP64) when at
 // most three tracked keys lie in the band and no slot pair holds two of them; and
 // queued for the re-screen otherwise.
-template <typename T, int KS, int PT, int NW>
+template <typename T, int KS, int PT, int NW, bool R16 = false>
 __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) void k_screen_bf16(
     const T* __restrict__ X, int64_t n, int d, int k, const uint16_t* __restrict__ cb16,
     const float* __restrict__ cnB, const float* __restrict__ cw, const double* __restrict__ c64,
@@ -2513,7 +2513,21 @@ __global__ __launch_bounds__(64 * NW, PT == 1 && NW == 8 && KS == 8 ? 4 : 2) voi
   // by then); FP32 data is rounded as it is loaded, at the start of the batch.
   constexpr bool EARLY = sizeof(T) == 2;
   v8bf x[PT][KS];
+  // R16 (chosen by the host): every row is KS*16 BF16 dims on a 16-byte
+  // boundary, so each piece is one 16-byte load with no checks (a point past
+  // n reads row 0; its column of the MFMAs is never used).
   auto load_rows = [&](int64_t b0) {
+    if constexpr (R16) {
+#pragma unroll
+      for (int p = 0; p < PT; ++p) {
+        const int64_t e = b0 + (int64_t)(wave * PT + p) * 32 + pc;
+        const T* row = X + (e < n ? e : 0) * d + 8 * h;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+          x[p][s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(row + 16 * s));
+      }
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
       const int64_t e = b0 + (int64_t)(wave * PT + p) * 32 + pc;
@@ -4203,7 +4217,18 @@ static int64_t resident_blocks(K kernel, size_t lds, int cus, int threads = 256)
 
 // Screen kernel for ks 16-dim K steps: PT point tiles per wave, NW waves a block.
 template <typename T, typename F>
-static void visit_screen(int ks, F&& f) {
+static void visit_screen(int ks, F&& f, bool r16 = false) {
+  if constexpr (sizeof(T) == 2) {
+    if (r16) {
+      switch (ks) {
+        case 1: f(k_screen_bf16<T, 1, 2, 4, true>); return;
+        case 2: f(k_screen_bf16<T, 2, 2, 4, true>); return;
+        case 4: f(k_screen_bf16<T, 4, 1, 8, true>); return;
+        case 8: f(k_screen_bf16<T, 8, 2, 8, true>); return;
+        default: f(k_screen_bf16<T, 16, 1, 8, true>); return;
+      }
+    }
+  }
   switch (ks) {
     case 1: f(k_screen_bf16<T, 1, 2, 4>); break;
     case 2: f(k_screen_bf16<T, 2, 2, 4>); break;
@@ -4211,6 +4236,10 @@ static void visit_screen(int ks, F&& f) {
     case 8: f(k_screen_bf16<T, 8, 2, 8>); break;
     default: f(k_screen_bf16<T, 16, 1, 8>); break;
   }
+}
+// The screen's whole-row loads apply: BF16 rows of exactly ks*16 dims, 16-byte aligned.
+static bool screen_r16(int dtype, int32_t d, int ks, const void* X) {
+  return dtype == 1 && d == ks * 16 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
 }
 // threads (64 NW) and points (NW PT 32) per block of the screen for each K-step count
 constexpr int screen_threads(int ks) { return (ks == 4 || ks >= 8) ? 512 : 256; }
@@ -4232,8 +4261,9 @@ static int64_t plan_blocks(const PassPlan& p, int cus) {
   int64_t r = 0;
   auto f = [&](auto kern) { r = resident_blocks(kern, p.lds_assign, cus); };
   if (p.bf16)
-    visit_screen<T>(p.ks,
-                    [&](auto kern) { r = resident_blocks(kern, 0, cus, screen_threads(p.ks)); });
+    visit_screen<T>(
+        p.ks, [&](auto kern) { r = resident_blocks(kern, 0, cus, screen_threads(p.ks)); },
+        sizeof(T) == 2 && p.d == p.ks * 16);
   else if (p.fscreen && p.fsplit) visit_pair<T>(p.kd, p.nt, p.kd == p.d, f);
   else if (p.fscreen) visit_fscreen<T>(p.kd, p.nt, p.kd == p.d, f);
   else if (p.mfma) visit_mfma<T>(p.kd, p.nt, p.kd == p.d, f);
@@ -4417,13 +4447,15 @@ static void sorted_update(const PassBufs& b, const PassPlan& p, const int32_t* g
 template <typename T>
 static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* gate,
                           hipStream_t s) {
-  visit_screen<T>(p.ks, [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(screen_threads(p.ks)), 0, s,
-                       (const T*)b.X, b.n, b.d,
-                       b.k, (const uint16_t*)b.cb16, (const float*)b.cnB, (const float*)b.cw,
-                       (const double*)b.c64, b.st, gate, b.labels, b.queue, b.qthr, b.rq_c,
-                       b.Jpart, b.upart);
-  });
+  visit_screen<T>(
+      p.ks,
+      [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)p.blocks), dim3(screen_threads(p.ks)), 0, s,
+                           (const T*)b.X, b.n, b.d, b.k, (const uint16_t*)b.cb16,
+                           (const float*)b.cnB, (const float*)b.cw, (const double*)b.c64, b.st,
+                           gate, b.labels, b.queue, b.qthr, b.rq_c, b.Jpart, b.upart);
+      },
+      screen_r16(sizeof(T) == 2 ? 1 : 0, b.d, p.ks, b.X));
 }
 
 // The screen's re-rank list, in FP64.
