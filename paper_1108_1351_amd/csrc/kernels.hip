@@ -3602,10 +3602,23 @@ __global__ __launch_bounds__(256, 3) void k_batch_screen(const BatchHead* __rest
     const int64_t iA = p0 + pc, iB = p0 + 32 + pc;
     const bool vA = iA < n, vB = iB < n;
     v8bf xA[KS], xB[KS];
+    const bool rows16 = d == KD && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+    if (rows16) {
+      // whole rows of KD dims: one 16-byte load per piece (a point past n
+      // reads row 0; its column of the MFMAs is not used)
+      const uint16_t* rA = X + (vA ? iA : 0) * d + 8 * h;
+      const uint16_t* rB = X + (vB ? iB : 0) * d + 8 * h;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      xA[s] = load8_bf16<uint16_t>(X + (vA ? iA : 0) * d, 16 * s + 8 * h, d, vA);
-      xB[s] = load8_bf16<uint16_t>(X + (vB ? iB : 0) * d, 16 * s + 8 * h, d, vB);
+      for (int s = 0; s < KS; ++s) {
+        xA[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(rA + 16 * s));
+        xB[s] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(rB + 16 * s));
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        xA[s] = load8_bf16<uint16_t>(X + (vA ? iA : 0) * d, 16 * s + 8 * h, d, vA);
+        xB[s] = load8_bf16<uint16_t>(X + (vB ? iB : 0) * d, 16 * s + 8 * h, d, vB);
+      }
     }
     const float B = st->B, cmax = st->cmax, dcn = st->dcn * 1.01f;
     // FP32 accumulation of 2 KD products and the bias, any rounding of the
@@ -3809,7 +3822,8 @@ __global__ __launch_bounds__(256, 3) void k_batch_screen(const BatchHead* __rest
 #pragma unroll 2
         for (int s = 0; s < KS; ++s) {
           const int t0 = 16 * s + 8 * h;
-          const uint4 w = __builtin_bit_cast(uint4, load8_bf16<uint16_t>(xr, t0, d, true));
+          const uint4 w = rows16 ? *reinterpret_cast<const uint4*>(xr + t0)
+                                 : __builtin_bit_cast(uint4, load8_bf16<uint16_t>(xr, t0, d, true));
           const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
           double cv[8];
 #pragma unroll
