@@ -3804,83 +3804,142 @@ __global__ __launch_bounds__(256, 3) void k_batch_screen(const BatchHead* __rest
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       __builtin_amdgcn_wave_barrier();
     }
+    // Candidates of pair points join the lists (a full point's list was filled
+    // by the second sweep).  The listed points (one to kBatchCands candidates)
+    // are then decided in FP64 by groups of 16 lanes, one point per group at a
+    // time: lane l of a group holds dims 8l .. 8l+7 of the point and of each
+    // candidate row, so both are read as whole rows; the 16 partial sums are
+    // added in a fixed tree.  Lowest index on equal distances.
+    __shared__ uint8_t lpts[4][64];
+    __shared__ uint8_t blab[4][64];
+    __shared__ int lcnt[4];
+    bool listedv[2];
+    if (__ballot(pairv[0] || pairv[1] || fullv[0] || fullv[1])) {
+      if (lane == 0) lcnt[wave] = 0;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const int64_t i = p == 0 ? iA : iB;
-      const bool valid = p == 0 ? vA : vB;
-      const bool pair = pairv[p];
-      const int nc = ncv[p];
-      int bi1 = best[p];
-      const int* gq = p == 0 ? ga : gb;
-      // FP64 direct form over the lane half's dims, then both halves'.  The
-      // row is read again (it is in cache), eight dims at a time, so that the
-      // loop need not be unrolled over registers held for the whole tail.
-      auto dist64 = [&](int j) {
-        const double* cj = b.c64 + (int64_t)j * d;
-        const uint16_t* xr = X + (valid ? i : 0) * d;
-        double part = 0.0;
-#pragma unroll 2
-        for (int s = 0; s < KS; ++s) {
-          const int t0 = 16 * s + 8 * h;
-          const uint4 w = rows16 ? *reinterpret_cast<const uint4*>(xr + t0)
-                                 : __builtin_bit_cast(uint4, load8_bf16<uint16_t>(xr, t0, d, true));
-          const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
-          double cv[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) cv[q] = cj[t0 + q < d ? t0 + q : 0];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const float xv = (q & 1) ? bf16_hi(w4[q >> 1]) : bf16_lo(w4[q >> 1]);
-            const double e = t0 + q < d ? (double)xv - cv[q] : 0.0;
-            part = __builtin_fma(e, e, part);
-          }
-        }
-        return part + __shfl_xor(part, 32);
-      };
-      // Candidates of pair and full points go into the point's list (a full
-      // point's list was filled by the second sweep); FP64 decides among them
-      // (lowest index on equal values).
-      const bool full = fullv[p];
-      if (__ballot(pair || full)) {
-        if (pair && h == 0) {
+      for (int p = 0; p < 2; ++p) {
+        const int* gq = p == 0 ? ga : gb;
+        if (pairv[p] && h == 0) {
 #pragma unroll
           for (int q = 0; q < 3; ++q)
-            if (q < nc) cand[wave][p][pc][q] = (uint8_t)(gq[q] & GM);
-          ccnt[wave][p][pc] = nc;
+            if (q < ncv[p]) cand[wave][p][pc][q] = (uint8_t)(gq[q] & GM);
+          ccnt[wave][p][pc] = ncv[p];
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int cnt = (pair || full) ? ccnt[wave][p][pc] : 0;
-        const bool listed = (pair || full) && cnt >= 1 && cnt <= kBatchCands;
-        int qn = listed ? cnt : 0;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int cnt = (pairv[p] || fullv[p]) ? ccnt[wave][p][pc] : 0;
+        listedv[p] = (pairv[p] || fullv[p]) && cnt >= 1 && cnt <= kBatchCands;
+        if (listedv[p] && h == 0) lpts[wave][atomicAdd(&lcnt[wave], 1)] = (uint8_t)(32 * p + pc);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int nl = lcnt[wave];
+      const int grp = lane >> 4, sub = lane & 15, t0 = 8 * sub;
+      const int64_t p0w = tile * 256 + (int64_t)wave * 64;
+      for (int l0 = 0; l0 < nl; l0 += 4) {
+        const int li = l0 + grp;
+        const bool act = li < nl;
+        const int slot = act ? lpts[wave][li] : 0;
+        const int pp = slot >> 5, ps = slot & 31;
+        const int cnt = act ? ccnt[wave][pp][ps] : 0;
+        const uint16_t* xr = X + (act ? p0w + slot : 0) * d;
+        const uint4 w = rows16 ? *reinterpret_cast<const uint4*>(xr + t0)
+                               : __builtin_bit_cast(uint4, load8_bf16<uint16_t>(xr, t0, d, true));
+        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+        int qn = cnt;
         for (int o = 32; o > 0; o >>= 1) qn = max(qn, __shfl_xor(qn, o));
         double bd = INFINITY;
         int bj = INT_MAX;
         for (int q = 0; q < qn; ++q) {
-          const bool use = listed && q < cnt;
-          const int jq = use ? (int)cand[wave][p][pc][q] : bi1;
-          const double dq = dist64(jq);
-          if (use && (dq < bd || (dq == bd && jq < bj))) {
-            bd = dq;
-            bj = jq;
+          const bool use = act && q < cnt;
+          const int j = use ? (int)cand[wave][pp][ps][q] : 0;
+          const double* cj = b.c64 + (int64_t)j * d;
+          double cv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) cv[e] = cj[t0 + e < d ? t0 + e : 0];
+          double part = 0.0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float xv = (e & 1) ? bf16_hi(w4[e >> 1]) : bf16_lo(w4[e >> 1]);
+            const double df = t0 + e < d ? (double)xv - cv[e] : 0.0;
+            part = __builtin_fma(df, df, part);
+          }
+          part += __shfl_xor(part, 8);
+          part += __shfl_xor(part, 4);
+          part += __shfl_xor(part, 2);
+          part += __shfl_xor(part, 1);
+          if (use && (part < bd || (part == bd && j < bj))) {
+            bd = part;
+            bj = j;
           }
         }
-        if (listed) bi1 = bj < k ? bj : 0;
-        pcnt += __popcll(__ballot(listed && h == 0));
-        const bool rest = full && !listed;
-        if (__ballot(rest)) {
-          int lab = bi1;
-          ucnt += wave_fp64_fallback<uint16_t>(rest && h == 0, i, X, d, k, b.c64, lab);
-          // the half-0 lane decided: both halves take its label
-          lab = __shfl(lab, pc);
-          if (rest) bi1 = lab;
-        }
+        if (act && sub == 0) blab[wave][slot] = (uint8_t)(bj < k ? bj : 0);
       }
-      const double D = dist64(valid ? bi1 : 0);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      listedv[0] = listedv[1] = false;
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int64_t i = p == 0 ? iA : iB;
+      const bool valid = p == 0 ? vA : vB;
+      int bi1 = best[p];
+      const bool listed = listedv[p];
+      if (listed) bi1 = blab[wave][32 * p + pc];
+      pcnt += __popcll(__ballot(listed && h == 0));
+      const bool rest = fullv[p] && !listed;
+      if (__ballot(rest)) {
+        int lab = bi1;
+        ucnt += wave_fp64_fallback<uint16_t>(rest && h == 0, i, X, d, k, b.c64, lab);
+        // the half-0 lane decided: both halves take its label
+        lab = __shfl(lab, pc);
+        if (rest) bi1 = lab;
+      }
       if (valid && h == 0) {
-        Jacc += D;
         if (b.labels) b.labels[i] = bi1;
+        blab[wave][32 * p + pc] = (uint8_t)bi1;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // J: the FP64 direct form of every point at its label, by groups of 16
+    // lanes as above (whole rows, a fixed tree over the lanes)
+    {
+      const int grp = lane >> 4, sub = lane & 15, t0 = 8 * sub;
+      const int64_t p0w = tile * 256 + (int64_t)wave * 64;
+#pragma unroll 1
+      for (int l0 = 0; l0 < 64; l0 += 4) {
+        const int slot = l0 + grp;
+        const bool ok = p0w + slot < n;
+        const int j = ok ? (int)blab[wave][slot] : 0;
+        const uint16_t* xr = X + (ok ? p0w + slot : 0) * d;
+        const uint4 w = rows16 ? *reinterpret_cast<const uint4*>(xr + t0)
+                               : __builtin_bit_cast(uint4, load8_bf16<uint16_t>(xr, t0, d, true));
+        const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+        const double* cj = b.c64 + (int64_t)j * d;
+        double cv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cv[e] = cj[t0 + e < d ? t0 + e : 0];
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float xv = (e & 1) ? bf16_hi(w4[e >> 1]) : bf16_lo(w4[e >> 1]);
+          const double df = t0 + e < d ? (double)xv - cv[e] : 0.0;
+          part = __builtin_fma(df, df, part);
+        }
+        part += __shfl_xor(part, 8);
+        part += __shfl_xor(part, 4);
+        part += __shfl_xor(part, 2);
+        part += __shfl_xor(part, 1);
+        if (ok && sub == 0) Jacc += part;
       }
     }
     block_sum_J(Jacc, ucnt, pcnt, b.Jpart, b.upart, tile);
