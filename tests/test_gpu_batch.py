@@ -32,8 +32,11 @@ PROBLEMS = [
     (1_000, 3, 7, "f32", 0.5, 3, (40, 40), (0.0, 0.0)),
     (5_003, 32, 64, "bf16", 0.1, 4, (10, 10), (1e-4, 1e-4)),
     (12_000, 128, 100, "bf16", 0.05, 5, (6, 8), (1e-4, 1e-4)),
-    (40_000, 16, 256, "f32", 0.01, 6, (8, 8), (1e-4, 1e-4)),   # sums by global atomics
+    (40_000, 16, 256, "f32", 0.01, 6, (8, 8), (1e-4, 1e-4)),   # sums beyond LDS: k_batch_sums
     (700, 64, 9, "f32", 1.0, 7, (15, 15), (1e-6, 1e-6)),
+    (15_000, 64, 100, "f32", 0.05, 8, (6, 6), (1e-4, 1e-4)),   # k_batch_sums, whole pieces
+    (9_001, 37, 220, "f32", 0.05, 9, (5, 5), (1e-4, 1e-4)),    # k_batch_sums, element loads
+    (30_000, 128, 200, "bf16", 0.02, 10, (4, 6), (1e-4, 1e-4)),  # four center ranges
 ]
 
 
