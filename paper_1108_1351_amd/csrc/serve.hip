@@ -4,10 +4,13 @@
 // Every admitted problem runs the method of section 2 of Salman et al.
 // (arXiv 1108.1351) on its own data -- sampling, Lloyd passes on the subset,
 // Lloyd passes on all points, final labels -- but the passes of all problems
-// advance together: one round is one batched pass, a launch of the assignment
-// kernel per register-tile shape plus one finalize launch for every problem,
-// replayed from a captured HIP graph.  Problems move between stages on the
-// host between rounds, from a compact status array copied back per round.
+// advance together: one batched pass is a launch of the assignment kernel per
+// shape (the FP32 kernel per register tile, the BF16 screen per K-step count),
+// one cluster-sum launch and one finalize launch for every problem.  Chunks of
+// such passes are replayed from captured HIP graphs; problems move between
+// stages on the host between chunks, from a compact status array copied back
+// per chunk (a problem whose stage ends inside a chunk is skipped by the
+// device until the chunk ends).
 #include <condition_variable>
 #include <deque>
 #include <map>
