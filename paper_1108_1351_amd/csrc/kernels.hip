@@ -1091,6 +1091,83 @@ __global__ __launch_bounds__(256) void k_lab_scatter(const int32_t* __restrict__
   }
 }
 
+// As k_lab_scatter, for k <= kScatterLdsK: each range of S points of chunk b
+// is first sorted by label in LDS (histogram, exclusive scan, placement), then
+// written out in that order, so the indices of one label go to consecutive
+// words of perm (runs of about S/k) instead of one scattered word per point.
+// LDS: base, lcnt, lst (k words each) and the sorted range (S words); S <= 2^14
+// and k <= 2^18 so a sorted entry packs (label << 14) | offset.
+__global__ __launch_bounds__(256) void k_lab_scatter_lds(const int32_t* __restrict__ labels,
+                                                         int64_t n, int k, int64_t chunk,
+                                                         int64_t G, int S,
+                                                         const long long* __restrict__ off,
+                                                         uint32_t* __restrict__ perm,
+                                                         const int32_t* __restrict__ gate) {
+  if (gated(gate)) return;
+  extern __shared__ uint32_t sm[];
+  uint32_t* base = sm;          // next position of label j in perm for this chunk
+  uint32_t* lcnt = sm + k;      // the range's count of label j
+  uint32_t* lst = sm + 2 * k;   // its first place in the sorted range (after
+                                // placement: one past its last)
+  uint32_t* lsrt = sm + 3 * k;  // the range in label order
+  __shared__ uint32_t wtot[4];
+  const int64_t b = blockIdx.x, i0 = b * chunk, i1 = min(n, i0 + chunk);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int kc = (k + 255) / 256;  // scan entries per thread
+  for (int j = t; j < k; j += 256) base[j] = (uint32_t)off[(int64_t)j * G + b];
+  for (int64_t s0 = i0; s0 < i1; s0 += S) {
+    const int m = (int)min((int64_t)S, i1 - s0);
+    for (int j = t; j < k; j += 256) lcnt[j] = 0u;
+    __syncthreads();
+    for (int e = t; e < m; e += 256) {
+      const int j = labels[s0 + e];
+      if ((unsigned)j < (unsigned)k) atomicAdd(&lcnt[j], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of lcnt into lst; thread t takes entries [t*kc, t*kc + kc)
+    uint32_t own = 0;
+    for (int q = 0; q < kc; ++q) {
+      const int j = t * kc + q;
+      if (j < k) own += lcnt[j];
+    }
+    uint32_t inc = own;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(inc, o);
+      if (lane >= o) inc += v;
+    }
+    if (lane == 63) wtot[wave] = inc;
+    __syncthreads();
+    uint32_t pre = inc - own;
+    for (int w = 0; w < wave; ++w) pre += wtot[w];
+    for (int q = 0; q < kc; ++q) {
+      const int j = t * kc + q;
+      if (j < k) {
+        lst[j] = pre;
+        pre += lcnt[j];
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < m; e += 256) {
+      const int j = labels[s0 + e];
+      if ((unsigned)j < (unsigned)k) {
+        const uint32_t pos = atomicAdd(&lst[j], 1u);
+        lsrt[pos] = ((uint32_t)j << 14) | (uint32_t)e;
+      }
+    }
+    __syncthreads();
+    const uint32_t tot = (wtot[0] + wtot[1]) + (wtot[2] + wtot[3]);
+    for (uint32_t q = t; q < tot; q += 256) {
+      const uint32_t w = lsrt[q];
+      const int j = (int)(w >> 14);
+      const uint32_t first = lst[j] - lcnt[j];
+      perm[(uint64_t)base[j] + (q - first)] = (uint32_t)(s0 + (int64_t)(w & 0x3fffu));
+    }
+    __syncthreads();
+    for (int j = t; j < k; j += 256) base[j] += lcnt[j];
+    __syncthreads();
+  }
+}
+
 // The E center coordinates of a lane (FP64).
 template <int E>
 __device__ __forceinline__ void load_center(const double* __restrict__ c64, int j, int d, int col,
@@ -4346,6 +4423,14 @@ static int64_t plan_blocks(const PassPlan& p, int cus) {
   return r;
 }
 
+// Points per LDS-sorted range of k_lab_scatter_lds for k labels (its LDS, 3k + S
+// words plus 4 static ones, within 64 KB; S a multiple of 256 in [4096, 2^14)),
+// or 0 when k is too large and the plain scatter runs.
+static int scatter_range(int k) {
+  const int S = std::min((1 << 14) - 256, (16384 - 16 - 3 * k) / 256 * 256);
+  return k >= 1 && S >= 4096 ? S : 0;
+}
+
 PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
                    size_t lds_limit, int cus) {
   PassPlan p{};
@@ -4422,6 +4507,11 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
       // chunk) pairs at most; lane groups of pg positions, about 65536 groups
       const int64_t want = (int64_t)(((double)rows * (double)k) / (double)(1 << 22)) + 1;
       p.sort_chunk = std::max<int64_t>(4096, (want + 255) / 256 * 256);
+      // chunks of at least one LDS-sorted range (longer runs of one label in
+      // the scatter's writes) while that leaves 512 chunks or more
+      const int64_t S = scatter_range(k);
+      if (S > 0)
+        p.sort_chunk = std::max(p.sort_chunk, std::min(S, rows / 512 / 256 * 256));
       p.sort_chunks = (rows + p.sort_chunk - 1) / p.sort_chunk;
       p.pg = std::min<int64_t>(1 << 13, std::max<int64_t>(64, (rows + 65535) / 65536));
     }
@@ -4496,8 +4586,15 @@ static void sorted_update(const PassBufs& b, const PassPlan& p, const int32_t* g
                      (const long long*)b.stot, gate);
   hipLaunchKernelGGL(k_run_starts, dim3((unsigned)((b.k + 256) / 256)), dim3(256), 0, s,
                      (const long long*)b.scnt, b.k, G, b.n, b.rstart, gate);
-  hipLaunchKernelGGL(k_lab_scatter, dim3((unsigned)G), dim3(256), lds, s,
-                     (const int32_t*)b.labels, b.n, b.k, p.sort_chunk, G, b.scnt, b.perm, gate);
+  const int S = scatter_range(b.k);
+  if (S > 0)
+    hipLaunchKernelGGL(k_lab_scatter_lds, dim3((unsigned)G), dim3(256),
+                       (size_t)(3 * b.k + S) * 4, s, (const int32_t*)b.labels, b.n, b.k,
+                       p.sort_chunk, G, S, (const long long*)b.scnt, b.perm, gate);
+  else
+    hipLaunchKernelGGL(k_lab_scatter, dim3((unsigned)G), dim3(256), lds, s,
+                       (const int32_t*)b.labels, b.n, b.k, p.sort_chunk, G, b.scnt, b.perm,
+                       gate);
   const int E = row_vec(b.dtype, b.d, b.X), glog = row_glog(b.d, E);
   const int64_t groups = (b.n + p.pg - 1) / p.pg;
   const int64_t waves = (groups + (64 >> glog) - 1) / (64 >> glog);
