@@ -4514,6 +4514,22 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
         p.sort_chunk = std::max(p.sort_chunk, std::min(S, rows / 512 / 256 * 256));
       p.sort_chunks = (rows + p.sort_chunk - 1) / p.sort_chunk;
       p.pg = std::min<int64_t>(1 << 13, std::max<int64_t>(64, (rows + 65535) / 65536));
+      // every group walks pg positions, so the groups are sized to fill whole
+      // generations of resident run-sum blocks (a last, partly filled one
+      // leaves most of the GPU idle); rows of whole 16-byte pieces assumed,
+      // and any pg in [64, 2^13] is correct
+      const int E = dtype == 0 ? 4 : 8;
+      if (((int64_t)d * (dtype == 0 ? 4 : 2)) % 16 == 0) {
+        const int glog = row_glog(d, E);
+        const int64_t ncb = (d + (E << glog) - 1) / (E << glog);
+        const int64_t res = dtype == 0 ? resident_blocks(k_run_sums<float, 4>, 0, cus)
+                                       : resident_blocks(k_run_sums<uint16_t, 8>, 0, cus);
+        const int64_t gpg = std::max<int64_t>(1, res / ncb) * 4 * (64 >> glog);
+        int64_t gens = std::max<int64_t>(1, (65536 + gpg / 2) / gpg);
+        gens = std::max(gens, (rows + gpg * 8192 - 1) / (gpg * 8192));
+        p.pg = std::min<int64_t>(1 << 13,
+                                 std::max<int64_t>(64, (rows + gens * gpg - 1) / (gens * gpg)));
+      }
     }
   }
   // a persistent grid: no more blocks than stay resident at once
