@@ -14,7 +14,7 @@ import torch
 import oracle
 import synth
 from gpu_helpers import (CTOL, GAP, JTOL, j_atol, assert_centers, assert_labels, assert_step,
-                         exempt_mask, to_device, widen)
+                         exempt_mask, sums_from_labels, to_device, widen)
 
 pytestmark = pytest.mark.gpu
 
@@ -510,3 +510,30 @@ def test_step_more_labels_than_lds_counters():
     out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
     ref = oracle.step(Xh, C)
     assert_step(out, Xh, C, ref, jtol=1e-9, name="17000 labels")
+
+
+def test_step_label_sort_ranges_per_chunk():
+    """k = 4090 labels over 4.5M rows: the label sort's chunks (4,608 rows) are
+    longer than the ranges it sorts in LDS (4,096 rows at this k), so each chunk
+    takes two ranges, and the last chunk is ragged.  Labels of sampled rows are
+    the oracle's; counts, sums, new centers and J are checked against FP64 sums
+    over the GPU's own labels (a point written twice or not at all by the
+    scatter would change a cluster's sum by far more than the quantum)."""
+    n, d, k = 4_500_001, 16, 4090
+    Xh = _mixture(n, d, 60, seed=23)
+    C = _centers_from(Xh, k, seed=24, jitter=0.3)
+    print(f"[label sort ranges] n={n} d={d} k={k}", flush=True)
+    out = km.km_step(to_device(Xh), torch.from_numpy(C).cuda())
+    lab = out["labels"].cpu().numpy()
+    rows = np.sort(np.random.default_rng(25).choice(n, 20_000, replace=False))
+    assert_labels(lab[rows], np.ascontiguousarray(Xh[rows]), C, name="sampled rows")
+    S_l, A_l, N_l = sums_from_labels(Xh, lab, k)
+    assert np.array_equal(out["N"].cpu().numpy(), N_l)
+    X = widen(Xh)
+    quantum = 2.0 ** (np.floor(np.log2(np.abs(X).max())) - 29)
+    S = out["S"].cpu().numpy()
+    assert np.all(np.abs(S - S_l) <= N_l[:, None] * quantum + 1e-12 * A_l)
+    C_exp = np.where(N_l[:, None] > 0, S_l / np.maximum(N_l, 1)[:, None], C)
+    assert_centers(out["C_new"].cpu().numpy(), C_exp, Xh, tol=1e-9, name="C_new")
+    J_l = float(((X - C[lab]) ** 2).sum())
+    assert abs(out["J"] - J_l) <= 1e-9 * J_l, (out["J"], J_l)
