@@ -2920,8 +2920,20 @@ __global__ __launch_bounds__(256) void k_rerank_list(
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     const int rn = (int)min<int64_t>(RB, n - r0);
-    for (int o = threadIdx.x; o < rn; o += 256)
-      if (labels[r0 + o] < 0) list[atomicAdd(&cnt, 1)] = (uint16_t)o;
+    // the thread's labels are loaded four at a time before their list updates,
+    // so the loads overlap instead of each waiting behind the previous atomic
+#pragma unroll 1
+    for (int u0 = 0; u0 < RB / 256; u0 += 4) {
+      int lv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int o = (u0 + u) * 256 + (int)threadIdx.x;
+        lv[u] = o < rn ? labels[r0 + o] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (lv[u] < 0) list[atomicAdd(&cnt, 1)] = (uint16_t)((u0 + u) * 256 + threadIdx.x);
+    }
     __syncthreads();
     const int m = cnt;
     // the 16 lanes of a group take the same q (uniform loop within a group)
@@ -4535,6 +4547,15 @@ PassPlan plan_pass(int64_t rows, int32_t d, int32_t k, int dtype, int precision,
   // a persistent grid: no more blocks than stay resident at once
   const int64_t res = dtype == 0 ? plan_blocks<float>(p, cus) : plan_blocks<uint16_t>(p, cus);
   p.blocks = std::max<int64_t>(1, std::min<int64_t>({work, res, (int64_t)kMaxBlocks}));
+  if (p.bf16) {
+    // the re-rank's blocks walk ranges of the points in a grid-stride loop:
+    // all of them resident, so none waits for a second round of blocks
+    auto rr = [&](auto kern) { return resident_blocks(kern, 0, cus); };
+    if (dtype == 0)
+      p.rr_blocks = p.ks <= 8 ? rr(k_rerank_list<float, 8>) : rr(k_rerank_list<float, 16>);
+    else
+      p.rr_blocks = p.ks <= 8 ? rr(k_rerank_list<uint16_t, 8>) : rr(k_rerank_list<uint16_t, 16>);
+  }
   return p;
 }
 
@@ -4648,8 +4669,9 @@ static void dispatch_bf16(const PassBufs& b, const PassPlan& p, const int32_t* g
 template <typename T>
 static void dispatch_rerank(const PassBufs& b, const PassPlan& p, const int32_t* gate,
                             hipStream_t s) {
-  // ranges of 4096 points, one block each (up to 2048 blocks in the grid)
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 4095) / 4096, 2048));
+  // ranges of 4096 points, one block each (no more blocks than stay resident)
+  const int64_t cap = p.rr_blocks > 0 ? std::min<int64_t>(p.rr_blocks, 2048) : 2048;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.n + 4095) / 4096, cap));
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(g), dim3(256), 0, s, (const T*)b.X, b.n, b.d, b.k,
                        (const float*)b.cw, (const double*)b.c64, (const PassState*)b.st, gate,

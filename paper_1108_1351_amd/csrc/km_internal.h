@@ -192,6 +192,7 @@ struct PassPlan {
   int64_t pg;           // positions per lane group of the run sums
   size_t lds_assign;
   int ktile;         // centers per LDS tile (split assign)
+  int64_t rr_blocks = 0;  // resident blocks of the re-rank kernel (BF16 screen path)
 };
 
 // The pass keeps a BF16 copy of the centers (prep_bf16, then the finalize).
