@@ -1006,11 +1006,21 @@ __global__ __launch_bounds__(256) void k_lab_count(const int32_t* __restrict__ l
     for (int j = threadIdx.x; j < k; j += 256) h[j] = 0u;
     __syncthreads();
   }
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-    const int j = labels[i];
-    if ((unsigned)j >= (unsigned)k) continue;
-    if (lds) atomicAdd(&h[j], 1u);
-    else atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[(int64_t)j * G + b]), 1ull);
+  // labels four at a time per thread, so the loads overlap
+  for (int64_t i0t = i0 + threadIdx.x; i0t < i1; i0t += 1024) {
+    int jv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = i0t + 256 * u;
+      jv[u] = i < i1 ? labels[i] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = jv[u];
+      if ((unsigned)j >= (unsigned)k) continue;
+      if (lds) atomicAdd(&h[j], 1u);
+      else atomicAdd(reinterpret_cast<unsigned long long*>(&cnt[(int64_t)j * G + b]), 1ull);
+    }
   }
   if (lds) {
     __syncthreads();
@@ -1119,9 +1129,17 @@ __global__ __launch_bounds__(256) void k_lab_scatter_lds(const int32_t* __restri
     const int m = (int)min((int64_t)S, i1 - s0);
     for (int j = t; j < k; j += 256) lcnt[j] = 0u;
     __syncthreads();
-    for (int e = t; e < m; e += 256) {
-      const int j = labels[s0 + e];
-      if ((unsigned)j < (unsigned)k) atomicAdd(&lcnt[j], 1u);
+    // labels four at a time per thread, so the loads overlap
+    for (int e0 = t; e0 < m; e0 += 1024) {
+      int jv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 256 * u;
+        jv[u] = e < m ? labels[s0 + e] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if ((unsigned)jv[u] < (unsigned)k) atomicAdd(&lcnt[jv[u]], 1u);
     }
     __syncthreads();
     // exclusive scan of lcnt into lst; thread t takes entries [t*kc, t*kc + kc)
@@ -1147,12 +1165,19 @@ __global__ __launch_bounds__(256) void k_lab_scatter_lds(const int32_t* __restri
       }
     }
     __syncthreads();
-    for (int e = t; e < m; e += 256) {
-      const int j = labels[s0 + e];
-      if ((unsigned)j < (unsigned)k) {
-        const uint32_t pos = atomicAdd(&lst[j], 1u);
-        lsrt[pos] = ((uint32_t)j << 14) | (uint32_t)e;
+    for (int e0 = t; e0 < m; e0 += 1024) {
+      int jv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 256 * u;
+        jv[u] = e < m ? labels[s0 + e] : -1;
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if ((unsigned)jv[u] < (unsigned)k) {
+          const uint32_t pos = atomicAdd(&lst[jv[u]], 1u);
+          lsrt[pos] = ((uint32_t)jv[u] << 14) | (uint32_t)(e0 + 256 * u);
+        }
     }
     __syncthreads();
     const uint32_t tot = (wtot[0] + wtot[1]) + (wtot[2] + wtot[3]);
