@@ -76,9 +76,15 @@ typedef struct {
   double J_stage1;       /* J of the last fast-stage pass (over the subset, at that pass's centers) */
   int64_t dist_evals;    /* k*(m*iters[0] + n*iters[1]) + k*n: point-center distances the method needs */
   double shift[2];       /* last largest center movement of each stage */
-  int64_t uncertain;     /* labels decided by the FP64 check over all centers, summed over passes */
+  int64_t uncertain;     /* labels the screen could not settle among its best candidates, summed
+                            over passes: the FP64 check over all centers (FP32 and small-d
+                            paths); on the BF16 screen path the points queued for the
+                            re-screen, plus those it sends to the FP64 check */
   double seconds[3];     /* wall time of sampling, fast stage, slow stage + final labels */
-  int64_t fp64_pairs;    /* labels decided by FP64 distances to the best two candidates */
+  int64_t fp64_pairs;    /* labels decided among a short candidate list, summed over passes:
+                            FP64 distances to the best two (FP32 and small-d paths); on the
+                            BF16 screen path the points re-ranked among two to four
+                            candidates, plus re-screened points decided in FP64 */
 } km_info;
 
 typedef struct {
