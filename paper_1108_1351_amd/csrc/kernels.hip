@@ -1211,7 +1211,7 @@ __device__ __forceinline__ void load_center(const double* __restrict__ c64, int 
 // once at the end into jslots.  Every sum is an exact integer, so neither the
 // order of the label sort nor that of the atomics changes a bit of the result.
 template <typename T, int E>
-__global__ __launch_bounds__(256) void k_run_sums(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_run_sums(
     const T* __restrict__ X, int64_t n, int d, int k, int glog, int64_t pg,
     const uint32_t* __restrict__ perm, const long long* __restrict__ start,
     const double* __restrict__ c64, const PassState* __restrict__ st,
@@ -1258,18 +1258,32 @@ __global__ __launch_bounds__(256) void k_run_sums(
       atomicAdd(reinterpret_cast<unsigned long long*>(&row[d]), (unsigned long long)cnt);
     cnt = 0;
   };
-  constexpr int R = 8;  // rows in flight per group
+  // Rows in flight per group.  Whole 16-byte pieces stay packed until added,
+  // and only two are in flight, which fits the kernel in five waves per SIMD:
+  // the gathered rows are served faster by more resident groups than by
+  // deeper batches per group (8 rows at three waves per SIMD, or 16 at two,
+  // measured slower; the 8-element form spills a few registers at five waves
+  // and is still the fastest).
+  constexpr bool PK = E * sizeof(T) == 16;
+  constexpr int R = PK ? 2 : 8;
   // the label order's row indices of the next R positions, loaded one batch
   // ahead so that the row loads do not wait for them
   uint32_t pidx[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) pidx[r] = p0 + r < p1 ? perm[p0 + r] : 0u;
   for (int64_t p = p0; p < p1; p += R) {
-    float x[R][E];
+    uint4 xw[PK ? R : 1];
+    float xf[PK ? 1 : R][E];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const bool in = p + r < p1;
-      load_vec<T, E>(X + (int64_t)pidx[r] * d + col, in && act, x[r]);
+      const T* src = X + (int64_t)pidx[r] * d + col;
+      if constexpr (PK) {
+        xw[r] = make_uint4(0u, 0u, 0u, 0u);
+        if (in && act) xw[r] = *reinterpret_cast<const uint4*>(src);
+      } else {
+        load_vec<T, E>(src, in && act, xf[r]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) pidx[r] = p + R + r < p1 ? perm[p + R + r] : 0u;
@@ -1285,11 +1299,27 @@ __global__ __launch_bounds__(256) void k_run_sums(
           } while (pr >= run_end);
           load_center<E>(c64, j, d, col, act, c);
         }
+        float x[E];
+        if constexpr (PK) {
+          const uint32_t w4[4] = {xw[r].x, xw[r].y, xw[r].z, xw[r].w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if constexpr (sizeof(T) == 4) {
+              x[u] = __uint_as_float(w4[u]);
+            } else {
+              x[2 * u] = __uint_as_float(w4[u] << 16);
+              x[2 * u + 1] = __uint_as_float(w4[u] & 0xffff0000u);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) x[e] = xf[r][e];
+        }
         double part = 0.0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          acc[e] += (double)rintf(x[r][e] * scale);
-          const double df = (double)x[r][e] - c[e];
+          acc[e] += (double)rintf(x[e] * scale);
+          const double df = (double)x[e] - c[e];
           part = part + df * df;
         }
         const double q = rint(part * sj);
